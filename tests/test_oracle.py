@@ -1,0 +1,451 @@
+"""Pins of the ORACLE against things other than itself.
+
+Each test checks the oracle against what the paper or mathematics fixes:
+textbook values (LEB128, SplitMix64), closed forms (entropy bound), brute
+force on tiny inputs (byte-serial LZ77, recursive depth, byte-precise
+closure), hand-derived golden fixtures, and the paper's invariants (every
+offset lies behind the write position; a depth cap changes no decoded byte
+and leaves unforced blocks byte-identical; the history-free encoding emits no
+repeat command and decodes identically; encoding is deterministic).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import xxhash
+from hypothesis import given, settings, strategies as st
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- LEB128 --
+
+def test_leb128_textbook_values():
+    # DWARF / Wikipedia unsigned LEB128 example: 624485 -> E5 8E 26
+    assert oracle.leb_put(624485) == bytes([0xE5, 0x8E, 0x26])
+    assert oracle.leb_put(0) == b"\x00"
+    assert oracle.leb_put(127) == b"\x7f"
+    assert oracle.leb_put(128) == b"\x80\x01"
+    assert oracle.leb_put(2**64 - 1) == b"\xff" * 9 + b"\x01"
+    assert oracle.leb_get(bytes([0xE5, 0x8E, 0x26])) == (0, 624485, 3)
+
+
+def test_leb128_rejects_overflow_and_truncation():
+    assert oracle.leb_get(b"\xff" * 9 + b"\x02")[0] == oracle.E_CORRUPT  # > 64 bits
+    assert oracle.leb_get(b"\x80\x80")[0] == oracle.E_CORRUPT  # truncated
+    assert oracle.leb_get(b"\x80" * 10 + b"\x00")[0] == oracle.E_CORRUPT  # 11 bytes
+
+
+@given(st.integers(min_value=0, max_value=2**64 - 1))
+def test_leb128_roundtrip(v):
+    b = oracle.leb_put(v)
+    assert len(b) == max(1, math.ceil(v.bit_length() / 7))  # minimal form
+    assert oracle.leb_get(b) == (0, v, len(b))
+
+
+# ------------------------------------------------------------------- rANS --
+
+def _entropy_bits(sym):
+    c = np.bincount(sym, minlength=256).astype(np.float64)
+    p = c[c > 0] / sym.size
+    return float(-(c[c > 0] * np.log2(p)).sum())
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 100, 4096, 16384])
+@pytest.mark.parametrize("alpha", [2, 4, 30, 256])
+def test_rans_roundtrip(n, alpha):
+    rng = np.random.default_rng(n * 1000 + alpha)
+    p = rng.dirichlet(np.ones(alpha))
+    sym = rng.choice(alpha, size=n, p=p).astype(np.uint8) * (256 // alpha)
+    rec = oracle.stream_encode(sym)
+    rc, out, used = oracle.stream_decode(rec, max(n, 1))
+    assert rc == 0 and used == rec.size
+    assert np.array_equal(out, sym)
+
+
+@given(st.binary(min_size=2, max_size=3000), st.integers(min_value=0, max_value=6))
+@settings(max_examples=60, deadline=None)
+def test_rans_lane_count_does_not_change_symbols(data, lg):
+    sym = np.frombuffer(data, np.uint8)
+    if len(set(data)) < 2:
+        return
+    a = oracle.stream_encode(sym, force_rans=True, lanes_log2=0)
+    b = oracle.stream_encode(sym, force_rans=True, lanes_log2=lg)
+    assert b[5] == lg and b[4] == 2  # RANS record with K = 2^lg lanes
+    for rec in (a, b):
+        rc, out, _ = oracle.stream_decode(rec, sym.size)
+        assert rc == 0 and np.array_equal(out, sym)
+
+
+def test_rans_size_near_entropy_bound():
+    """rANS with 12-bit frequencies codes iid symbols within a few percent of
+    the order-0 entropy (closed form), plus the K final states."""
+    rng = np.random.default_rng(5)
+    for p in ([0.5, 0.25, 0.125, 0.125], [0.9, 0.05, 0.03, 0.02], [0.3, 0.3, 0.2, 0.1, 0.1]):
+        sym = rng.choice(len(p), size=200000, p=p).astype(np.uint8)
+        rec = oracle.stream_encode(sym, force_rans=True)
+        bound = _entropy_bits(sym) / 8
+        K = 1 << int(rec[5])
+        n_words = int.from_bytes(bytes(rec[8:12]), "little")
+        coded = 2 * n_words + 4 * K  # renormalisation words + final states
+        # no code beats the empirical order-0 entropy by more than the K
+        # states' 2^16 floor; 12-bit quantisation costs well under 1%
+        assert bound <= coded + 2 * K
+        assert coded <= bound * 1.01 + 4 * K + 64
+
+
+def test_rans_end_state_checks():
+    rng = np.random.default_rng(9)
+    sym = rng.integers(0, 4, 5000, dtype=np.uint8)
+    rec = oracle.stream_encode(sym, force_rans=True, lanes_log2=3)
+    rc, out, _ = oracle.stream_decode(rec, sym.size)
+    assert rc == 0
+    bad = rec.copy()
+    bad[12:16] = [0, 0, 0, 0]  # lane 0 state below 2^16
+    assert oracle.stream_decode(bad, sym.size)[0] == oracle.E_CORRUPT
+    bad = rec.copy()
+    nw = int.from_bytes(bytes(rec[8:12]), "little")
+    bad[8:12] = np.frombuffer((nw - 1).to_bytes(4, "little"), np.uint8)  # one word fewer
+    assert oracle.stream_decode(bad, sym.size)[0] == oracle.E_CORRUPT
+
+
+def test_stream_modes():
+    rec = oracle.stream_encode(np.full(77, 9, np.uint8))
+    assert rec[4] == 1 and rec[5] == 9 and rec.size == 8  # CONST
+    rec = oracle.stream_encode(np.zeros(0, np.uint8))
+    assert rec[4] == 0 and rec.size == 8  # empty RAW
+    rec = oracle.stream_encode(np.arange(256, dtype=np.uint8))  # incompressible -> RAW
+    assert rec[4] == 0
+
+
+# --------------------------------------------------------- periodic fill --
+
+def test_periodic_fill_equals_byte_serial_bruteforce():
+    """out[dst+k] = out[src + k mod dist] equals the textbook byte-at-a-time
+    LZ77 copy for every dist, len <= 64 (periodic-fill section)."""
+    rng = np.random.default_rng(1)
+    base = rng.integers(0, 256, 200, dtype=np.uint8)
+    for dist in range(1, 65):
+        for ln in range(1, 65):
+            src, dst = 70, 70 + dist
+            ref = bytearray(base.tobytes())
+            for k in range(ln):  # textbook LZ77: one byte at a time
+                ref[dst + k] = ref[src + k]
+            a = oracle.copy(base, dst, src, ln, periodic=True)
+            b = oracle.copy(base, dst, src, ln, periodic=False)
+            assert a.tobytes() == bytes(ref) == b.tobytes(), (dist, ln)
+
+
+# -------------------------------------------------------- golden fixtures --
+
+def _load_golden(name):
+    data, cmds, extra = None, [], {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.rstrip("\n")
+            if not line or line.startswith("#"):
+                continue
+            key, _, val = line.partition(":")
+            val = val.strip()
+            if key == "data":
+                data = val.encode()
+            elif key == "cmd":
+                kind, dst, ln, src, rep = map(int, val.split())
+                cmds.append((kind, dst, ln, src, rep))
+            else:
+                extra[key] = val
+    return data, cmds, extra
+
+
+def test_golden_history_walk():
+    data, cmds, ex = _load_golden("history_walk.txt")
+    assert len(data) == sum(c[2] for c in cmds)
+    arc = oracle.assemble(data, cmds)
+    assert oracle.decode(arc).tobytes() == data
+    s = oracle.block_streams(arc, 0)
+    assert s["cmd"].tobytes() == bytes.fromhex(ex["cmd_bytes"])
+    assert s["off"].tobytes() == bytes.fromhex(ex["off_bytes"])
+    assert s["len"].tobytes() == bytes.fromhex(ex.get("len_bytes", ""))
+    assert s["lit"].tobytes() == ex["lit_bytes"].encode()
+    parse = oracle.block_parse(arc, 0)
+    assert [int(x) for x in parse["src"][parse["kind"] == 2]] == [10, 11, 24]
+
+
+def test_golden_periodic_fill():
+    data, cmds, _ = _load_golden("periodic_fill.txt")
+    assert len(data) == sum(c[2] for c in cmds) == 64
+    arc = oracle.assemble(data, cmds)
+    for mode in (0, 1):
+        assert oracle.decode(arc, copy_mode=mode).tobytes() == data
+
+
+def test_golden_depth_chain():
+    data, cmds, ex = _load_golden("depth_chain.txt")
+    assert len(data) == sum(c[2] for c in cmds) == 64
+    arc = oracle.assemble(data, cmds)
+    assert oracle.decode(arc).tobytes() == data
+    d, mx = oracle.depths(arc)
+    assert list(d) == [int(x) for x in ex["depths"].split()] and mx == 3
+
+
+# ------------------------------------------------------------ round trips --
+
+def _roundtrip(x, **kw):
+    x = np.frombuffer(bytes(x), np.uint8) if isinstance(x, (bytes, bytearray)) else x
+    arc, st = oracle.encode(x, **kw)
+    inf = oracle.info(arc)
+    assert inf.n_bytes == x.size and inf.xxh3 == xxhash.xxh3_64_intdigest(x.tobytes())
+    for mode in (0, 1):
+        assert np.array_equal(oracle.decode(arc, copy_mode=mode), x)
+    return arc, st
+
+
+@pytest.mark.parametrize("x", [b"", b"a", b"ab", b"abc", b"\x00" * 5, bytes(range(256)) * 3])
+def test_roundtrip_tiny(x):
+    _roundtrip(x)
+
+
+@given(st.binary(max_size=5000))
+@settings(max_examples=80, deadline=None)
+def test_roundtrip_random_binary(x):
+    _roundtrip(x, block_size=4096)
+
+
+@given(st.lists(st.sampled_from(list(b"ACGTacgtN")), max_size=20000), st.integers(0, 1))
+@settings(max_examples=30, deadline=None)
+def test_roundtrip_random_dna_alphabet(x, no_rep):
+    _roundtrip(bytes(x), block_size=4096, no_rep=no_rep)
+
+
+def test_roundtrip_adversarial():
+    rng = np.random.default_rng(3)
+    cases = {
+        "not_block_multiple": synth.dna(3 * 16384 + 1234, 11),
+        "all_one_byte": np.full(70000, 65, np.uint8),
+        "text": synth.text(100000, 12),
+    }
+    for period in (1, 2, 3, 5, 9, 64, 153):  # tandem repeats, period 1..153
+        unit = rng.integers(0, 256, period, dtype=np.uint8)
+        cases[f"tandem{period}"] = np.tile(unit, 50000 // period + 1)[:50000]
+    for name, x in cases.items():
+        for kw in ({}, {"no_rep": 1}, {"min_match": 7}):
+            _roundtrip(x, **kw)
+
+
+def test_roundtrip_large_block_three_byte_varints():
+    x = np.full(200000, 7, np.uint8)
+    x[100] = 1
+    arc, st = _roundtrip(x, block_size=65536)
+    s = oracle.block_streams(arc, 1)
+    assert s["len"].size >= 3  # a block-long repeat needs a 3-byte LEB128 length
+
+
+# --------------------------------------------------------- special cases --
+
+def test_empty_input_has_no_blocks():
+    arc, _ = oracle.encode(b"")
+    inf = oracle.info(arc)
+    assert inf.n_blocks == 0 and inf.n_bytes == 0 and arc.size == 64 + 16
+
+
+def test_all_equal_input_is_one_literal_then_period_one_fills():
+    B = 16384
+    x = np.full(3 * B, 42, np.uint8)
+    arc, _ = _roundtrip(x)
+    p0 = oracle.block_parse(arc, 0)
+    assert [(int(c["kind"]), int(c["len"])) for c in p0] == [(0, 1), (2, B - 1)]
+    assert int(p0[1]["dst"] - p0[1]["src"]) == 1
+    for b in (1, 2):
+        pb = oracle.block_parse(arc, b)
+        assert len(pb) == 1 and pb[0]["kind"] == 2 and int(pb[0]["dst"] - pb[0]["src"]) == 1
+
+
+def test_min_match_above_n_is_all_literal():
+    x = synth.text(200, 4)
+    arc, st = _roundtrip(x, min_match=255)
+    assert st.n_matches == 0
+
+
+# ------------------------------------------------------------- invariants --
+
+def _all_cmds(arc):
+    inf = oracle.info(arc)
+    return np.concatenate([oracle.block_parse(arc, b) for b in range(inf.n_blocks)]) if inf.n_blocks else []
+
+
+def test_every_offset_lies_behind_the_write_position():
+    for x in (synth.dna(200000, 5), synth.text(200000, 6)):
+        arc, _ = oracle.encode(x)
+        c = _all_cmds(arc)
+        m = c[c["kind"] != 0]
+        assert np.all(m["src"] < m["dst"])
+        B = oracle.info(arc).block_size
+        assert np.all((c["dst"] + c["len"] - 1) // B == c["dst"] // B)  # never crosses a block
+
+
+def test_no_rep_emits_no_repeat_and_decodes_identically():
+    x = synth.dna(300000, 8)
+    a, sa = oracle.encode(x)
+    b, sb = oracle.encode(x, no_rep=1)
+    assert sa.n_rep > 0 and sb.n_rep == 0
+    assert np.all(_all_cmds(b)["kind"] != 2)
+    assert oracle.info(b).flags & 1
+    assert np.array_equal(oracle.decode(b), x)
+
+
+def test_encoding_is_deterministic():
+    x = synth.dna(200000, 9)
+    a, _ = oracle.encode(x)
+    b, _ = oracle.encode(x)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("cap", [2, 4, 8])
+def test_depth_cap_invariants(cap):
+    """Depth section: the cap bounds every depth, changes no decoded byte, and
+    the blocks whose streams differ from the uncapped encoding are exactly the
+    blocks holding a forced position (the byte-level comparison)."""
+    x = synth.dna(600000, 10)
+    base, sb = oracle.encode(x, block_size=4096)
+    capped, sc, forced = oracle.encode_forced(x, block_size=4096, depth_cap=cap)
+    d, mx = oracle.depths(capped)
+    assert mx <= cap and sc.max_depth <= cap and sc.passes >= 2
+    assert np.array_equal(oracle.decode(capped), x)
+    assert oracle.info(capped).flags & 2
+    nb = oracle.info(base).n_blocks
+    differ = set()
+    for b in range(nb):
+        sa, sc_ = oracle.block_streams(base, b), oracle.block_streams(capped, b)
+        if not all(np.array_equal(sa[k], sc_[k]) for k in sa):
+            differ.add(b)
+    forced_blocks = set(np.unique(np.nonzero(forced)[0] // 4096).tolist())
+    assert len(forced_blocks) > 0 and int(forced.sum()) == sc.n_forced_bytes
+    assert differ == forced_blocks
+    assert len(differ) < nb
+
+
+# ------------------------------------------------- depth, levels, closure --
+
+def _writer_map(arc):
+    """Brute force: for every output byte, the index of the command that wrote it."""
+    c = _all_cmds(arc)
+    n = oracle.info(arc).n_bytes
+    w = np.zeros(n, np.int64)
+    for i, cmd in enumerate(c):
+        w[cmd["dst"]: cmd["dst"] + cmd["len"]] = i
+    return c, w
+
+
+def test_depth_matches_recursive_definition():
+    """depth(m) = 0 if all source bytes are literal, else 1 + max depth of the
+    matches that wrote them — evaluated recursively per byte, not by the
+    oracle's forward pass."""
+    for x in (synth.dna(60000, 21), synth.text(60000, 22)):
+        arc, _ = oracle.encode(x, block_size=4096)
+        c, w = _writer_map(arc)
+        memo = {}
+
+        def depth(i):
+            if i in memo:
+                return memo[i]
+            cmd = c[i]
+            dist = int(cmd["dst"] - cmd["src"])
+            best = -1
+            for q in range(int(cmd["src"]), int(cmd["src"]) + min(int(cmd["len"]), dist)):
+                j = int(w[q])
+                if c[j]["kind"] != 0:
+                    best = max(best, depth(j))
+            memo[i] = best + 1
+            return best + 1
+
+        import sys
+        sys.setrecursionlimit(100000)
+        want = [depth(i) for i in range(len(c)) if c[i]["kind"] != 0]
+        got, mx = oracle.depths(arc)
+        assert list(got) == want and mx == max(want, default=0)
+
+
+def test_closure_matches_bruteforce():
+    """Byte-precise closure: resolve each needed byte to the bytes it copies,
+    recursively, and collect the blocks touched."""
+    x = synth.dna(50000, 23)
+    arc, _ = oracle.encode(x, block_size=4096)
+    c, w = _writer_map(arc)
+    B = 4096
+    rng = np.random.default_rng(0)
+    for _ in range(6):
+        off = int(rng.integers(0, x.size - 1))
+        ln = int(rng.integers(1, min(9000, x.size - off) + 1))
+        need = set()
+        stack = list(range(off, off + ln))
+        while stack:
+            q = stack.pop()
+            if q in need:
+                continue
+            need.add(q)
+            cmd = c[w[q]]
+            if cmd["kind"] != 0:
+                k = q - int(cmd["dst"])
+                stack.append(int(cmd["src"]) + k % int(cmd["dst"] - cmd["src"]))
+        want = np.zeros(oracle.info(arc).n_blocks, np.uint8)
+        for q in need:
+            want[q // B] = 1
+        got, k = oracle.closure(arc, off, ln)
+        assert np.array_equal(got, want) and k == int(want.sum())
+
+
+def test_block_levels_bounds():
+    x = synth.dna(200000, 24)
+    arc, _ = oracle.encode(x, block_size=4096)
+    raw, msrc = oracle.block_levels(arc)
+    nb = oracle.info(arc).n_blocks
+    assert 0 <= msrc <= raw <= nb - 1
+
+
+# -------------------------------------------------------------- corruption --
+
+def test_corruption_returns_error_never_crashes():
+    x = synth.dna(40000, 25)
+    arc, _ = oracle.encode(x, block_size=4096)
+    rng = np.random.default_rng(7)
+    detected = 0
+    for trial in range(300):
+        bad = arc.copy()
+        if trial % 3 == 0:
+            bad = bad[: int(rng.integers(0, arc.size))]
+        else:
+            for _ in range(int(rng.integers(1, 4))):
+                bad[int(rng.integers(0, arc.size))] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        rc = oracle.decode_rc(bad)
+        assert rc in (0, oracle.E_CORRUPT, oracle.E_CHECKSUM, oracle.E_ARG)
+        detected += rc != 0
+    assert detected >= 290
+
+
+def test_forward_reference_is_rejected():
+    data = b"abcdefgh" * 4
+    arc = oracle.assemble(data, [(0, 0, 8, 0, 0), (1, 8, 24, 0, 0)])
+    assert np.array_equal(oracle.decode(arc), np.frombuffer(data, np.uint8))
+    with pytest.raises(oracle.OracleError):
+        oracle.assemble(data, [(0, 0, 8, 0, 0), (1, 8, 24, 8, 0)])  # src == dst
+
+
+# ------------------------------------------------------------- generators --
+
+def test_splitmix64_reference_value():
+    # SplitMix64 (Steele, Lea & Flood 2014) from state 0: first output
+    assert synth.splitmix64(0, 1)[0] == 0xE220A8397B1DCDAF
+
+
+def test_generators_are_deterministic_and_shaped():
+    a, b = synth.dna(100000, 1), synth.dna(100000, 1)
+    assert np.array_equal(a, b)
+    assert set(np.unique(a).tobytes()) <= set(b"ACGTacgtN")
+    low = np.isin(a, np.frombuffer(b"acgt", np.uint8)).mean()
+    assert 0.15 < low < 0.45  # ~30% lowercase runs
+    t = synth.text(100000, 3)
+    assert set(np.unique(t).tobytes()) <= set(b"abcdefghijklmnopqrstuvwxyz ,.?!\n")
