@@ -1,0 +1,158 @@
+/*
+ * aceapex.h — C ABI of the MI355X decoder for the absolute-offset LZ77 block
+ * format "AXP1".
+ *
+ * The operations follow the paper's statement of the problem (Introduction:
+ * hold a large archive compressed in device memory and decode on demand;
+ * Table 2: full device-resident decode; the random-access section: decode one
+ * 16 KB tile or a range of blocks from a resident archive):
+ *   aceapex_encode        host encoder (global match search, absolute offsets,
+ *                         fixed blocks, four streams per block — Setup);
+ *   aceapex_decode_all    device decode of a whole resident archive;
+ *   aceapex_decode_range  device decode of one byte range (its source closure);
+ *   aceapex_decode_batch  many archives / ranges in one persistent launch.
+ *
+ * Conventions
+ *   - Every function returns int: 0 (AX_OK) or a negative AX_E_* code.  No C++
+ *     exception crosses this boundary.  aceapex_last_error() gives a
+ *     thread-local detail string for the last failure on the calling thread.
+ *   - "h_" pointers are host memory, "d_" pointers are device memory of the
+ *     current HIP device.  The caller owns every buffer: archive, output,
+ *     workspace.  The library owns only opaque host handles.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Decode calls are asynchronous on that stream: they return after
+ *     enqueueing; argument and launch errors are returned synchronously,
+ *     format errors found on the device are recorded in a status word in the
+ *     workspace (first error wins) and read by aceapex_decoder_status.  After a
+ *     decode whose status is nonzero the output contents are unspecified.
+ *   - One host thread per decoder handle at a time; concurrent decodes on one
+ *     handle need distinct workspaces.  Decodes that share a workspace must be
+ *     ordered (same stream).
+ *   - Block sizes accepted by the device decoder: 4096, 8192, 16384 bytes.
+ */
+#ifndef ACEAPEX_H
+#define ACEAPEX_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  AX_OK = 0,
+  AX_E_ARG = -1,         /* bad argument (null pointer, size too small, ...) */
+  AX_E_CORRUPT = -2,     /* the archive violates the format */
+  AX_E_UNSUPPORTED = -3, /* valid but outside what this build decodes */
+  AX_E_CAPACITY = -4,    /* caller buffer or workspace too small */
+  AX_E_HIP = -5,         /* a HIP runtime call failed */
+  AX_E_RANGE = -6,       /* byte range outside the archive */
+  AX_E_DEVICE = -7,      /* device-side failure other than corruption (e.g. a wait limit) */
+  AX_E_NOMEM = -8        /* host allocation failed */
+};
+
+const char* aceapex_strerror(int code);
+const char* aceapex_last_error(void);
+
+/* ------------------------------------------------------------ encoding --- */
+
+/* Encoder parameters (defaults in parentheses).
+ *   block_size             output block size, power of two 4096..65536 (16384)
+ *   min_match              shortest match (4)
+ *   no_rep                 1 = never emit repeat commands; the paper's
+ *                          history-free encoding (0)
+ *   depth_cap              0 = none; else re-encode until no match is deeper
+ *                          than depth_cap — the forced-literal cap of the
+ *                          depth section (0)
+ *   hash_bits              hash-chain head table size (22)
+ *   chain_depth            candidates walked per position (32)
+ *   rans_min_syms_per_lane S of the rANS lane rule (128)
+ *   off_cost               an explicit-offset match must be at least
+ *                          min_match + off_cost * LEB128 bytes of its offset (2)
+ *   window_log             0 = candidates anywhere behind; else only within
+ *                          2^window_log bytes behind the position (0)
+ *   threads                encoder threads, 0 = hardware concurrency (0) */
+typedef struct {
+  uint32_t block_size, min_match, no_rep, depth_cap, hash_bits, chain_depth;
+  uint32_t rans_min_syms_per_lane, off_cost, window_log, threads;
+} aceapex_encode_params;
+
+typedef struct {
+  uint64_t n_bytes, n_blocks, comp_bytes, n_commands, n_matches, n_rep, n_match_bytes, n_lit_bytes;
+  uint32_t max_depth, passes;
+} aceapex_encode_stats;
+
+void aceapex_encode_params_default(aceapex_encode_params* p);
+
+/* Upper bound on the container size for n input bytes. */
+int aceapex_encode_bound(uint64_t n, const aceapex_encode_params* p, uint64_t* bound);
+
+/* Encode h_src[0..n) into h_dst[0..dst_cap); *dst_len receives the size.
+ * stats may be NULL.  Deterministic: the bytes do not depend on `threads`. */
+int aceapex_encode(const uint8_t* h_src, uint64_t n, const aceapex_encode_params* p, uint8_t* h_dst,
+                   uint64_t dst_cap, uint64_t* dst_len, aceapex_encode_stats* stats);
+
+/* ------------------------------------------------------------- reading --- */
+
+typedef struct {
+  uint64_t n_bytes;       /* decoded size */
+  uint64_t n_blocks;
+  uint64_t archive_bytes; /* header + index + payload */
+  uint64_t header_bytes;  /* header + index: what aceapex_decoder_create needs on the host */
+  uint64_t payload_bytes;
+  uint64_t n_matches;     /* MATCH + REP commands in the archive */
+  uint64_t xxh3;          /* XXH3-64 of the decoded bytes */
+  uint32_t block_size, min_match, flags, depth_cap;
+} aceapex_info;
+
+/* Parse the header from at least the first 64 bytes (h_len >= 64). The index
+ * is not needed. */
+int aceapex_read_info(const uint8_t* h_prefix, uint64_t h_len, aceapex_info* info);
+
+/* ------------------------------------------------------------ decoding --- */
+
+typedef struct aceapex_decoder aceapex_decoder;
+
+/* Create a decoder for an archive resident in device memory.
+ *   h_header  host copy of the header and index (info.header_bytes bytes);
+ *             read once here, not retained.
+ *   d_archive the whole archive in device memory (archive_len bytes); must
+ *             stay valid and unchanged for the life of the handle.
+ * Errors: AX_E_CORRUPT (bad header/index), AX_E_UNSUPPORTED (block size). */
+int aceapex_decoder_create(const uint8_t* h_header, uint64_t h_len, const uint8_t* d_archive,
+                           uint64_t archive_len, aceapex_decoder** out);
+void aceapex_decoder_destroy(aceapex_decoder* dec);
+int aceapex_decoder_info(const aceapex_decoder* dec, aceapex_info* info);
+
+/* Device workspace bytes for aceapex_decode_all (256-byte aligned start). */
+int aceapex_decoder_workspace(const aceapex_decoder* dec, uint64_t* bytes);
+
+/* Copy modes for the match layer:
+ *   AX_COPY_PERIODIC  self-overlapping matches run as periodic fills
+ *                     out[dst+k] = out[src + k mod dist], many lanes per match
+ *                     (periodic-fill section);
+ *   AX_COPY_SERIAL    the ablation: one lane per match, byte after byte. */
+enum { AX_COPY_PERIODIC = 0, AX_COPY_SERIAL = 1 };
+
+/* Decode the whole archive into d_out[0..n_bytes).
+ * d_work / work_len: device workspace of at least aceapex_decoder_workspace
+ * bytes.  Asynchronous on `stream`. */
+int aceapex_decode_all(aceapex_decoder* dec, uint8_t* d_out, uint64_t out_cap, void* d_work, uint64_t work_len,
+                       int copy_mode, void* stream);
+
+/* Stage timing of the last decode on this handle (HIP events on `stream`),
+ * in milliseconds: entropy (rANS of the four streams), parse (commands,
+ * literal placement, token emission), copy (match layer). Blocks on the
+ * events. */
+int aceapex_decoder_stage_ms(aceapex_decoder* dec, float* ans_ms, float* parse_ms, float* copy_ms);
+/* 1 = record stage events on later decodes (adds three event records). */
+int aceapex_decoder_set_timing(aceapex_decoder* dec, int enable);
+
+/* Read the device status word of a workspace after the work queued on
+ * `stream`: synchronises `stream`.  *dev_err is 0 or an AX_E_* code;
+ * *bad_block is the first failing block (or ~0). */
+int aceapex_decoder_status(aceapex_decoder* dec, void* d_work, void* stream, int32_t* dev_err,
+                           uint64_t* bad_block);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

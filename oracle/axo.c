@@ -64,6 +64,7 @@ void axo_params_default(axo_params* p) {
   p->chain_depth = 32;
   p->rans_min_syms_per_lane = 128;
   p->off_cost = 2;
+  p->window_log = 0;
 }
 
 /* ------------------------------------------------------------ buffers --- */
@@ -397,6 +398,7 @@ static int check_params(const axo_params* p) {
   if (p->block_size < 4096 || p->block_size > 65536 || (p->block_size & (p->block_size - 1))) return AXO_E_ARG;
   if (p->min_match < 1 || p->min_match > 255) return AXO_E_ARG;
   if (p->hash_bits < 10 || p->hash_bits > 26) return AXO_E_ARG;
+  if (p->window_log > 40) return AXO_E_ARG;
   return AXO_OK;
 }
 
@@ -460,7 +462,9 @@ static int encode_pass(const uint8_t* in, uint64_t n, const axo_params* p, const
       }
       if (pos + 4 <= n && maxlen > 0) {
         int64_t cand = head[hash4(in + pos, p->hash_bits)];
+        uint64_t win = p->window_log ? (1ull << p->window_log) : 0;
         for (uint32_t c = 0; c < p->chain_depth && cand >= 0; c++) {
+          if (win && (uint64_t)cand + win < pos) break; /* outside the window */
           uint64_t l = match_len(in, (uint64_t)cand, pos, maxlen);
           if (l > labs) { labs = l; src_abs = (uint64_t)cand; }
           if (l == maxlen) break;

@@ -44,6 +44,8 @@ typedef struct {
   uint32_t rans_min_syms_per_lane; /* S in the lane rule */
   uint32_t off_cost;               /* an explicit-offset match must be at least
                                       min_match + off_cost * (LEB128 bytes of src) long */
+  uint32_t window_log;             /* 0: candidates anywhere behind; else only
+                                      those at most 2^window_log bytes behind */
 } axo_params;
 
 void axo_params_default(axo_params* p);

@@ -1,0 +1,204 @@
+"""MI355X decoder for the absolute-offset LZ77 block format (AXP1).
+
+Thin ctypes binding of `libaceapex.so` (the C ABI in include/aceapex.h):
+argument marshalling only.  Every step of a decode runs in the library's HIP
+kernels; PyTorch supplies device memory and the stream.  There is no CPU
+fallback: without the built library every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaceapex.so")
+_lib = None
+
+AX_OK, AX_E_ARG, AX_E_CORRUPT, AX_E_UNSUPPORTED, AX_E_CAPACITY = 0, -1, -2, -3, -4
+AX_E_HIP, AX_E_RANGE, AX_E_DEVICE, AX_E_NOMEM = -5, -6, -7, -8
+COPY_PERIODIC, COPY_SERIAL = 0, 1
+
+EXPORTS = [
+    "aceapex_strerror", "aceapex_last_error", "aceapex_encode_params_default", "aceapex_encode_bound",
+    "aceapex_encode", "aceapex_read_info", "aceapex_decoder_create", "aceapex_decoder_destroy",
+    "aceapex_decoder_info", "aceapex_decoder_workspace", "aceapex_decode_all", "aceapex_decoder_stage_ms",
+    "aceapex_decoder_set_timing", "aceapex_decoder_status",
+]
+
+
+class AceapexError(RuntimeError):
+    def __init__(self, code, what):
+        lib = _load()
+        detail = lib.aceapex_last_error().decode(errors="replace")
+        super().__init__(f"{what}: {lib.aceapex_strerror(code).decode()} ({code}) {detail}")
+        self.code = code
+
+
+class EncodeParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "block_size", "min_match", "no_rep", "depth_cap", "hash_bits", "chain_depth",
+        "rans_min_syms_per_lane", "off_cost", "window_log", "threads")]
+
+
+class EncodeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "n_bytes", "n_blocks", "comp_bytes", "n_commands", "n_matches", "n_rep", "n_match_bytes",
+        "n_lit_bytes")] + [("max_depth", ctypes.c_uint32), ("passes", ctypes.c_uint32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "n_bytes", "n_blocks", "archive_bytes", "header_bytes", "payload_bytes", "n_matches", "xxh3")] + [
+        (n, ctypes.c_uint32) for n in ("block_size", "min_match", "flags", "depth_cap")]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, vp, u64, u32 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    u8p = P(ctypes.c_uint8)
+    L.aceapex_strerror.argtypes = [ctypes.c_int]
+    L.aceapex_strerror.restype = ctypes.c_char_p
+    L.aceapex_last_error.argtypes = []
+    L.aceapex_last_error.restype = ctypes.c_char_p
+    L.aceapex_encode_params_default.argtypes = [P(EncodeParams)]
+    L.aceapex_encode_params_default.restype = None
+    L.aceapex_encode_bound.argtypes = [u64, P(EncodeParams), P(u64)]
+    L.aceapex_encode.argtypes = [u8p, u64, P(EncodeParams), u8p, u64, P(u64), P(EncodeStats)]
+    L.aceapex_read_info.argtypes = [u8p, u64, P(Info)]
+    L.aceapex_decoder_create.argtypes = [u8p, u64, vp, u64, P(vp)]
+    L.aceapex_decoder_destroy.argtypes = [vp]
+    L.aceapex_decoder_destroy.restype = None
+    L.aceapex_decoder_info.argtypes = [vp, P(Info)]
+    L.aceapex_decoder_workspace.argtypes = [vp, P(u64)]
+    L.aceapex_decode_all.argtypes = [vp, vp, u64, vp, u64, ctypes.c_int, vp]
+    L.aceapex_decoder_stage_ms.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float)]
+    L.aceapex_decoder_set_timing.argtypes = [vp, ctypes.c_int]
+    L.aceapex_decoder_status.argtypes = [vp, vp, vp, P(ctypes.c_int32), P(u64)]
+    _lib = L
+    return L
+
+
+def lib():
+    return _load()
+
+
+def _check(rc, what):
+    if rc != AX_OK:
+        raise AceapexError(rc, what)
+
+
+def _u8(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def encode_params(**kw):
+    p = EncodeParams()
+    _load().aceapex_encode_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, int(v))
+    return p
+
+
+def encode(data, stats=False, **kw):
+    """Host encode (aceapex_encode).  Returns the archive as a uint8 array."""
+    a = np.ascontiguousarray(np.frombuffer(data, np.uint8) if isinstance(data, (bytes, bytearray)) else data,
+                             dtype=np.uint8)
+    p = encode_params(**kw)
+    bound = ctypes.c_uint64()
+    _check(_load().aceapex_encode_bound(a.size, ctypes.byref(p), ctypes.byref(bound)), "encode_bound")
+    out = np.empty(bound.value, np.uint8)
+    n = ctypes.c_uint64()
+    st = EncodeStats()
+    _check(_load().aceapex_encode(_u8(a), a.size, ctypes.byref(p), _u8(out), out.size, ctypes.byref(n),
+                                  ctypes.byref(st)), "encode")
+    arc = out[: n.value].copy()
+    return (arc, st) if stats else arc
+
+
+def read_info(prefix):
+    a = np.ascontiguousarray(prefix[:64] if not isinstance(prefix, (bytes, bytearray)) else
+                             np.frombuffer(bytes(prefix[:64]), np.uint8), dtype=np.uint8)
+    inf = Info()
+    _check(_load().aceapex_read_info(_u8(a), a.size, ctypes.byref(inf)), "read_info")
+    return inf
+
+
+def _stream_ptr(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Decoder:
+    """A decoder for one archive resident in device memory.
+
+    h_archive: host bytes holding at least the header and index.
+    d_archive: torch.uint8 CUDA tensor holding the whole archive.
+    """
+
+    def __init__(self, h_archive, d_archive):
+        import torch
+
+        h = np.ascontiguousarray(h_archive, dtype=np.uint8)
+        self.info = read_info(h)
+        if h.size < self.info.header_bytes:
+            raise ValueError("host copy must hold the header and index")
+        if d_archive.dtype != torch.uint8 or not d_archive.is_cuda:
+            raise ValueError("d_archive must be a CUDA uint8 tensor")
+        self._d_archive = d_archive  # keep alive
+        self._h = ctypes.c_void_p()
+        _check(_load().aceapex_decoder_create(_u8(h), int(self.info.header_bytes), ctypes.c_void_p(d_archive.data_ptr()),
+                                              d_archive.numel(), ctypes.byref(self._h)), "decoder_create")
+        ws = ctypes.c_uint64()
+        _check(_load().aceapex_decoder_workspace(self._h, ctypes.byref(ws)), "decoder_workspace")
+        self.workspace_bytes = ws.value
+        self._work = None
+        self.device = d_archive.device
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.aceapex_decoder_destroy(self._h)
+            self._h = None
+
+    def workspace(self):
+        import torch
+
+        if self._work is None:
+            self._work = torch.empty(max(256, self.workspace_bytes), dtype=torch.uint8, device=self.device)
+        return self._work
+
+    def set_timing(self, on=True):
+        _check(_load().aceapex_decoder_set_timing(self._h, int(bool(on))), "set_timing")
+
+    def decode_all(self, out=None, copy_mode=COPY_PERIODIC, stream=None, work=None):
+        """Enqueue a full decode; returns the output tensor (async)."""
+        import torch
+
+        n = int(self.info.n_bytes)
+        if out is None:
+            out = torch.empty(max(16, n), dtype=torch.uint8, device=self.device)
+        w = self.workspace() if work is None else work
+        _check(_load().aceapex_decode_all(self._h, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                          ctypes.c_void_p(w.data_ptr()), w.numel(), int(copy_mode),
+                                          _stream_ptr(stream)), "decode_all")
+        return out[:n] if out.numel() != n else out
+
+    def status(self, stream=None, work=None):
+        err = ctypes.c_int32()
+        bad = ctypes.c_uint64()
+        w = self.workspace() if work is None else work
+        _check(_load().aceapex_decoder_status(self._h, ctypes.c_void_p(w.data_ptr()), _stream_ptr(stream),
+                                              ctypes.byref(err), ctypes.byref(bad)), "decoder_status")
+        return err.value, bad.value
+
+    def stage_ms(self):
+        a, p, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        _check(_load().aceapex_decoder_stage_ms(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(c)),
+               "stage_ms")
+        return a.value, p.value, c.value

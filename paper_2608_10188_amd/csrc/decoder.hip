@@ -1,0 +1,944 @@
+// Device decoder of the AXP1 absolute-offset LZ77 block format for gfx950.
+//
+// Three kernels per window of blocks (the paper's ANS / parse / copy split,
+// Table 2):
+//   k_ans    one wave64 per (block, stream): order-0 rANS of the literal,
+//            length, offset and command streams with the slot table in LDS;
+//            renormalisation words are handed to the lanes that need them by
+//            ballot + prefix count over a register window of the word stream.
+//   k_parse  one workgroup per block: commands are parsed 256 at a time by
+//            block-wide prefix scans (positions, literal positions, value
+//            indices) and an associative scan of the four-entry distance
+//            history (each command is a map on history tuples); literal runs
+//            are placed into an LDS tile that is written out with 16-byte
+//            stores; matches become tokens (src, dst, len).
+//   k_copy   the match layer: waves take chunks of 64 tokens in output order
+//            from a ticket counter and copy every token whose source bytes
+//            are final (a readiness bitmap, one bit per output byte), as a
+//            periodic fill out[dst+k] = out[src + k mod dist]
+//            (periodic-fill section); long tokens are copied by the whole
+//            wave.  A token only waits on bytes below its own destination,
+//            written by literals or by tokens with lower tickets, so the
+//            schedule follows the dependency levels without a level plan.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "aceapex.h"
+#include "ax_common.h"
+
+namespace {
+
+constexpr uint32_t kMaxB = 16384;           // largest block the device path decodes
+constexpr uint32_t kParseThreads = 256;
+constexpr uint32_t kCopyWaves = 4;          // waves per k_copy workgroup
+constexpr uint32_t kLongToken = 48;         // tokens at least this long are copied by the whole wave
+constexpr uint64_t kTagRef = 1ull << 63;    // history-map slot holding an input index
+
+struct DevStatus {
+  int32_t err;
+  uint32_t pad0;
+  unsigned long long bad_block;
+  uint32_t ticket;
+  uint32_t pad1[59];
+};
+static_assert(sizeof(DevStatus) == 256, "status block is 256 bytes");
+
+__device__ inline void report(DevStatus* st, int code, uint64_t block) {
+  if (atomicCAS(&st->err, 0, code) == 0) atomicExch(&st->bad_block, (unsigned long long)block);
+}
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
+__device__ inline uint32_t ld32(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
+__device__ inline uint64_t ld64(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }
+
+// ------------------------------------------------------------------ k_ans --
+
+struct AnsArgs {
+  const uint8_t* arc;        // archive base
+  uint64_t payload_at;       // byte offset of the payload in the archive
+  uint64_t first_block;      // window start
+  uint32_t n_items;          // blocks in this window
+  uint32_t B;
+  uint8_t* lit;              // scratch, B per slot
+  uint8_t* cmd;              // scratch, B per slot
+  uint8_t* off;              // scratch, off_cap per slot
+  uint8_t* len;              // scratch, len_cap per slot
+  uint32_t off_cap, len_cap;
+  uint32_t* nsym;            // 4 per slot
+  DevStatus* st;
+};
+
+// Wave-level exclusive prefix sum of a u32.
+__device__ inline uint32_t wave_excl_sum(uint32_t v, uint32_t* total) {
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane_id() >= (uint32_t)o) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+__global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
+  __shared__ uint8_t symtab[ax::kProbScale];
+  __shared__ uint32_t fctab[256];     // f | cum << 16, indexed by symbol
+  __shared__ uint16_t cumtab[257];    // cum of the k-th present symbol, sentinel 4096
+  __shared__ uint8_t symlist[256];    // k-th present symbol
+
+  const uint32_t item = blockIdx.x % a.n_items;
+  const uint32_t stream = blockIdx.x / a.n_items;  // 0 LIT, 1 LEN, 2 OFF, 3 CMD
+  const uint64_t b = a.first_block + item;
+  const uint32_t lane = lane_id();
+  uint8_t* const outs[4] = {a.lit + uint64_t(item) * a.B, a.len + uint64_t(item) * a.len_cap,
+                            a.off + uint64_t(item) * a.off_cap, a.cmd + uint64_t(item) * a.B};
+  const uint32_t caps[4] = {a.B, a.len_cap, a.off_cap, a.B};
+  uint8_t* out = outs[stream];
+  const uint32_t cap = caps[stream];
+  uint32_t* nsym = a.nsym + 4 * item + stream;
+
+  const uint64_t* idx = reinterpret_cast<const uint64_t*>(a.arc + 64);
+  const uint64_t o0 = idx[b], o1 = idx[b + 1];
+  const uint8_t* blk = a.arc + a.payload_at + o0;
+  const uint64_t blen = o1 - o0;  // validated on the host: >= 16, 16-aligned
+  uint64_t at = 16;
+  for (uint32_t k = 0; k < stream; ++k) at += ld32(blk + 4 * k);
+  const uint32_t rlen = ld32(blk + 4 * stream);
+  if (at + rlen > blen || rlen < 8 || (rlen & 3)) {
+    if (lane == 0) { report(a.st, AX_E_CORRUPT, b); *nsym = 0; }
+    return;
+  }
+  const uint8_t* rec = blk + at;
+  const uint32_t n = ld32(rec), mode = rec[4], pa = rec[5], pb = rec[6];
+  if (n > cap) {
+    if (lane == 0) { report(a.st, AX_E_CORRUPT, b); *nsym = 0; }
+    return;
+  }
+  if (mode == 0) {  // raw: copy 4 bytes per lane per step
+    if (8 + uint64_t(n) > rlen) {
+      if (lane == 0) { report(a.st, AX_E_CORRUPT, b); *nsym = 0; }
+      return;
+    }
+    const uint32_t words = (n + 3) / 4;
+    for (uint32_t w = lane; w < words; w += 64)
+      reinterpret_cast<uint32_t*>(out)[w] = reinterpret_cast<const uint32_t*>(rec + 8)[w];
+    if (lane == 0) *nsym = n;
+    return;
+  }
+  if (mode == 1) {  // constant
+    const uint32_t v = pa * 0x01010101u, words = (n + 3) / 4;
+    for (uint32_t w = lane; w < words; w += 64) reinterpret_cast<uint32_t*>(out)[w] = v;
+    if (lane == 0) *nsym = n;
+    return;
+  }
+  bool bad = mode != 2 || pa > ax::kMaxLanesLog2 || rlen < 12;
+  const uint32_t K = 1u << (pa & 7), present = pb + 1;
+  bad |= present < 2;
+  uint64_t p = 12;
+  const uint32_t nw = bad ? 0 : ld32(rec + 8);
+  const uint64_t states_at = p;
+  p += 4ull * K;
+  const uint64_t words_at = p;
+  p = (p + 2ull * nw + 3) & ~3ull;
+  const uint64_t set_at = p;
+  p += present <= 32 ? present : 32;
+  p = (p + 1) & ~1ull;
+  const uint64_t freq_at = p;
+  p = (p + 2ull * present + 3) & ~3ull;
+  bad |= p != rlen;
+  if (bad) {
+    if (lane == 0) { report(a.st, AX_E_CORRUPT, b); *nsym = 0; }
+    return;
+  }
+  // --- table: lane l holds up to four present symbols in ascending order.
+  uint32_t mysym[4], myf[4], cnt = 0;
+  if (present <= 32) {
+    if (lane < present) { mysym[0] = rec[set_at + lane]; cnt = 1; }
+  } else {
+    const uint32_t bits = (rec[set_at + (lane >> 1)] >> ((lane & 1) * 4)) & 15u;
+    for (uint32_t j = 0; j < 4; ++j)
+      if (bits >> j & 1) mysym[cnt++] = lane * 4 + j;
+  }
+  uint32_t total_present;
+  const uint32_t rank0 = wave_excl_sum(cnt, &total_present);
+  uint32_t fsum = 0;
+  bad = total_present != present;
+  for (uint32_t j = 0; j < cnt; ++j) {
+    myf[j] = (rank0 + j < present) ? *reinterpret_cast<const uint16_t*>(rec + freq_at + 2 * (rank0 + j)) : 0;
+    bad |= myf[j] < 1 || myf[j] >= ax::kProbScale;
+    fsum += myf[j];
+  }
+  if (present <= 32 && cnt && lane > 0) bad |= rec[set_at + lane - 1] >= mysym[0];  // strictly ascending
+  uint32_t ftotal;
+  uint32_t cum = wave_excl_sum(fsum, &ftotal);
+  bad |= ftotal != ax::kProbScale;
+  if (__ballot(bad)) {
+    if (lane == 0) { report(a.st, AX_E_CORRUPT, b); *nsym = 0; }
+    return;
+  }
+  for (uint32_t j = 0; j < cnt; ++j) {
+    fctab[mysym[j]] = myf[j] | (cum << 16);
+    cumtab[rank0 + j] = uint16_t(cum);
+    symlist[rank0 + j] = uint8_t(mysym[j]);
+    cum += myf[j];
+  }
+  if (lane == 0) cumtab[present] = ax::kProbScale;
+  __syncthreads();
+  {  // slot -> symbol: lane l fills slots [64l, 64l+64) four at a time
+    const uint32_t s0 = lane * 64;
+    uint32_t lo = 0, hi = present - 1;  // last k with cumtab[k] <= s0
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (cumtab[mid] <= s0) lo = mid; else hi = mid - 1;
+    }
+    uint32_t k = lo, next = cumtab[k + 1];
+    for (uint32_t s = s0; s < s0 + 64; s += 4) {
+      uint32_t packed = 0;
+      for (uint32_t q = 0; q < 4; ++q) {
+        while (s + q >= next) { ++k; next = cumtab[k + 1]; }
+        packed |= uint32_t(symlist[k]) << (8 * q);
+      }
+      *reinterpret_cast<uint32_t*>(symtab + s) = packed;
+    }
+  }
+  __syncthreads();
+  // --- decode: lane j owns symbols j, j+K, ...
+  const uint16_t* words = reinterpret_cast<const uint16_t*>(rec + words_at);
+  uint32_t x = lane < K ? ld32(rec + states_at + 4 * lane) : ax::kRansLow;
+  bad = x < ax::kRansLow;
+  auto fetch = [&](uint32_t i) -> uint32_t { return i < nw ? uint32_t(words[i]) : 0u; };
+  uint32_t base = 0;  // window: wa = words[base+lane], wb = words[base+64+lane], wc = words[base+128+lane]
+  uint32_t wa = fetch(lane), wb = fetch(64 + lane), wc = fetch(128 + lane);
+  uint32_t ptr = 0;
+  const uint32_t steps = (n + K - 1) / K;
+  uint32_t i = lane;
+  for (uint32_t t = 0; t < steps; ++t, i += K) {
+    const bool act = lane < K && i < n;
+    const uint32_t slot = x & (ax::kProbScale - 1);
+    const uint32_t s = symtab[slot];
+    const uint32_t fc = fctab[s];
+    const uint32_t xn = (fc & 0xFFFFu) * (x >> ax::kProbBits) + slot - (fc >> 16);
+    const bool need = act && xn < ax::kRansLow;
+    const uint64_t m = __ballot(need);
+    const uint32_t q = ptr - base + lanes_below(m);  // < 128
+    const uint32_t va = __builtin_amdgcn_ds_bpermute(int((q & 63) << 2), int(wa));
+    const uint32_t vb = __builtin_amdgcn_ds_bpermute(int((q & 63) << 2), int(wb));
+    const uint32_t w = q < 64 ? va : vb;
+    if (act) {
+      x = need ? ((xn << 16) | w) : xn;
+      out[i] = uint8_t(s);
+    }
+    ptr += __popcll(m);
+    if (ptr - base >= 64) {
+      base += 64;
+      wa = wb;
+      wb = wc;
+      wc = fetch(base + 128 + lane);
+    }
+  }
+  bad |= lane < K && x != ax::kRansLow;
+  bad |= ptr != nw;
+  if (__ballot(bad)) {
+    if (lane == 0) report(a.st, AX_E_CORRUPT, b);
+  }
+  if (lane == 0) *nsym = n;
+}
+
+// ---------------------------------------------------------------- k_parse --
+
+struct ParseArgs {
+  const uint8_t* arc;
+  uint64_t n_bytes;
+  uint64_t first_block;
+  uint32_t n_items;
+  uint32_t B, mm;
+  const uint8_t *lit, *cmd, *off, *len;
+  uint32_t off_cap, len_cap;
+  const uint32_t* nsym;
+  uint64_t tok_first;        // cumulative match count at the window start
+  uint64_t tok_count;        // tokens in the window
+  uint64_t* tok;             // 2 u64 per token: src, dst | (len-1) << 48
+  uint8_t* out;              // decoded bytes (absolute positions)
+  uint32_t* bits;            // readiness bitmap of the window, 1 bit per byte
+  DevStatus* st;
+};
+
+struct Map4 {  // history map: slot = kTagRef | input index, or a distance
+  uint64_t s[4];
+};
+
+__device__ inline uint64_t map_pick(const Map4& f, uint64_t g) {
+  if (!(g & kTagRef)) return g;
+  const uint32_t j = uint32_t(g & 3);
+  return j == 0 ? f.s[0] : j == 1 ? f.s[1] : j == 2 ? f.s[2] : f.s[3];
+}
+// (later g) after (earlier f)
+__device__ inline Map4 map_after(const Map4& g, const Map4& f) {
+  Map4 h;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) h.s[i] = map_pick(f, g.s[i]);
+  return h;
+}
+__device__ inline Map4 map_identity() { return Map4{{kTagRef | 0, kTagRef | 1, kTagRef | 2, kTagRef | 3}}; }
+__device__ inline Map4 map_shfl_up(const Map4& m, int o) {
+  Map4 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r.s[i] = __shfl_up((unsigned long long)m.s[i], o, 64);
+  return r;
+}
+__device__ inline Map4 map_shfl(const Map4& m, int src) {
+  Map4 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r.s[i] = __shfl((unsigned long long)m.s[i], src, 64);
+  return r;
+}
+
+struct ParseShared {
+  uint8_t tile[kMaxB];
+  uint32_t litbits[kMaxB / 32];   // literal bytes of the block (output space)
+  uint32_t runbits[kMaxB / 32];   // run starts in the chunk's literal space
+  uint16_t runpre[kMaxB / 32];    // run starts in earlier words
+  uint16_t rundelta[kParseThreads];
+  uint64_t offval[kParseThreads];
+  uint32_t lenval[kParseThreads];
+  uint64_t wsum[4][2];
+  Map4 wmap[4];
+  uint32_t wterm[4];
+  int32_t wlast[4];
+  uint32_t leb_found, leb_cursor;
+  int bad;
+};
+
+// Block-wide exclusive scan of a u64 (sum), 256 threads.
+__device__ inline uint64_t block_excl_sum64(uint64_t v, uint64_t* total, ParseShared& sh, int slotk) {
+  const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+  uint64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t y = __shfl_up((unsigned long long)x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  if (lane == 63) sh.wsum[wv][slotk] = x;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint64_t t = sh.wsum[k][slotk];
+    if (k < wv) pre += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
+// Block-wide exclusive scan of history maps; returns the map before this
+// command and the chunk's total map.
+__device__ inline Map4 block_excl_map(const Map4& m, Map4* total, ParseShared& sh) {
+  const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+  Map4 x = m;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    Map4 y = map_shfl_up(x, o);
+    if (lane >= (uint32_t)o) x = map_after(x, y);
+  }
+  if (lane == 63) sh.wmap[wv] = x;
+  __syncthreads();
+  Map4 pre = map_identity(), tot = map_identity();
+  for (uint32_t k = 0; k < 4; ++k) {
+    if (k < wv) pre = map_after(sh.wmap[k], pre);
+    tot = map_after(sh.wmap[k], tot);
+  }
+  __syncthreads();
+  *total = tot;
+  Map4 incl_prev = map_shfl_up(x, 1);  // inclusive of the previous lane
+  Map4 ex = lane == 0 ? map_identity() : incl_prev;
+  return map_after(ex, pre);
+}
+
+// Decode `count` consecutive LEB128 values starting at byte *cursor of
+// src[0..n) into dst (u64) — all 256 threads. Returns false on a malformed
+// or missing value.  *cursor advances past the last value.
+__device__ bool leb_values(const uint8_t* src, uint32_t n, uint32_t* cursor, uint32_t count, uint64_t* dst,
+                           ParseShared& sh) {
+  const uint32_t t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+  uint32_t found = 0;
+  uint32_t win = *cursor;
+  uint32_t value_start = win;  // start of the value that is open at the window start
+  bool ok = true;
+  while (found < count) {
+    if (win >= n) { ok = false; break; }
+    const uint32_t pos = win + t;
+    const bool inb = pos < n;
+    const uint8_t byte = inb ? src[pos] : 0x80;
+    const bool term = inb && byte < 0x80;
+    const uint64_t m = __ballot(term);
+    const uint32_t before_in_wave = lanes_below(m);
+    const uint64_t lower = m & ((1ull << lane) - 1ull);
+    const int32_t prev_in_wave = lower ? int32_t(63 - __clzll(lower)) : -1;
+    if (lane == 0) {
+      sh.wterm[wv] = __popcll(m);
+      sh.wlast[wv] = m ? int32_t(63 - __clzll(m)) + int32_t(wv * 64) : -1;
+    }
+    __syncthreads();
+    uint32_t before = before_in_wave, all = 0;
+    int32_t prev = prev_in_wave >= 0 ? prev_in_wave + int32_t(wv * 64) : -1;
+    for (uint32_t k = 0; k < 4; ++k) {
+      if (k < wv) before += sh.wterm[k];
+      all += sh.wterm[k];
+    }
+    if (prev < 0)
+      for (int32_t k = int32_t(wv) - 1; k >= 0; --k)
+        if (sh.wlast[k] >= 0) { prev = sh.wlast[k]; break; }
+    if (term) {
+      const uint32_t vi = found + before;
+      const uint32_t start = prev >= 0 ? win + uint32_t(prev) + 1 : value_start;
+      if (vi < count) {
+        if (pos + 1 - start > 10) {
+          ok = false;
+        } else {
+          uint64_t v = 0;
+          for (uint32_t q = start; q <= pos; ++q) v |= uint64_t(src[q] & 0x7F) << (7 * (q - start));
+          if (pos - start == 9 && src[pos] > 1) ok = false;
+          dst[vi] = v;
+          if (vi == count - 1) sh.leb_cursor = pos + 1;
+        }
+      }
+    }
+    // the value still open at the end of this window starts after its last terminator
+    int32_t last = -1;
+    for (int32_t k = 3; k >= 0; --k)
+      if (sh.wlast[k] >= 0) { last = sh.wlast[k]; break; }
+    if (last >= 0) value_start = win + uint32_t(last) + 1;
+    if (win + 256 - value_start > 10 && found + all < count) ok = false;  // a value longer than 10 bytes
+    found += all;
+    win += 256;
+    __syncthreads();
+  }
+  if (__syncthreads_or(!ok)) return false;
+  if (count) *cursor = sh.leb_cursor;
+  __syncthreads();
+  return true;
+}
+
+__global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
+  __shared__ ParseShared sh;
+  const uint32_t item = blockIdx.x, t = threadIdx.x;
+  const uint64_t b = a.first_block + item;
+  const uint32_t B = a.B, mm = a.mm;
+  const uint64_t bs = b * B;
+  const uint32_t blen = uint32_t(min<uint64_t>(B, a.n_bytes - bs));
+  const uint32_t n_lit = a.nsym[4 * item + 0], n_len = a.nsym[4 * item + 1];
+  const uint32_t n_off = a.nsym[4 * item + 2], n_cmd = a.nsym[4 * item + 3];
+  const uint8_t* cmd = a.cmd + uint64_t(item) * B;
+  const uint8_t* lit = a.lit + uint64_t(item) * B;
+  const uint8_t* offs = a.off + uint64_t(item) * a.off_cap;
+  const uint8_t* lens = a.len + uint64_t(item) * a.len_cap;
+  const uint64_t* mpre = reinterpret_cast<const uint64_t*>(a.arc + 64) + (a.n_bytes + B - 1) / B + 1;
+  const uint64_t tok_lo = mpre[b] - a.tok_first, tok_n = mpre[b + 1] - mpre[b];
+
+  for (uint32_t w = t; w < B / 32; w += kParseThreads) sh.litbits[w] = 0;
+  if (t == 0) sh.bad = (n_lit > B || n_cmd > B || n_len > a.len_cap || n_off > a.off_cap) ? 1 : 0;
+  __syncthreads();
+  bool failed = sh.bad != 0;
+
+  uint32_t dst = 0, litp = 0, offc = 0, lenc = 0;
+  uint64_t ntok = 0;
+  uint64_t hist[4] = {1, 2, 3, 4};
+  for (uint32_t c0 = 0; c0 < n_cmd && !failed; c0 += kParseThreads) {
+    const uint32_t i = c0 + t;
+    const bool valid = i < n_cmd;
+    const uint32_t c = valid ? cmd[i] : 0u;
+    const uint32_t kind = c & 3;
+    bool bad = valid && kind == 3;
+    const uint32_t v = kind == 2 ? (c >> 4) : (c >> 2);
+    const bool esc = valid && !bad && v == (kind == 2 ? 15u : 63u);
+    const bool is0 = valid && kind == 0, is1 = valid && kind == 1, is2 = valid && kind == 2;
+    const uint64_t packed = uint64_t(esc) | (uint64_t(is1) << 16) | (uint64_t(is0) << 32) | (uint64_t(is1 || is2) << 48);
+    uint64_t ctot;
+    const uint64_t cex = block_excl_sum64(packed, &ctot, sh, 0);
+    const uint32_t esc_i = uint32_t(cex & 0xFFFF), k1_i = uint32_t((cex >> 16) & 0xFFFF);
+    const uint32_t run_i = uint32_t((cex >> 32) & 0xFFFF), tok_i = uint32_t(cex >> 48);
+    const uint32_t n_esc = uint32_t(ctot & 0xFFFF), n_k1 = uint32_t((ctot >> 16) & 0xFFFF);
+    const uint32_t n_tokc = uint32_t(ctot >> 48);
+    // length and offset values of this chunk
+    uint64_t* lv64 = sh.offval;  // reuse: lengths first, then offsets
+    if (!leb_values(lens, n_len, &lenc, n_esc, lv64, sh)) { failed = true; break; }
+    if (t < n_esc) {
+      const uint64_t e = lv64[t];
+      sh.lenval[t] = e > B ? 0xFFFFFFFFu : uint32_t(e);
+    }
+    __syncthreads();
+    if (!leb_values(offs, n_off, &offc, n_k1, sh.offval, sh)) { failed = true; break; }
+    uint32_t len = 0;
+    if (valid) {
+      const uint32_t ext = esc ? sh.lenval[esc_i] : 0u;
+      bad |= ext == 0xFFFFFFFFu;
+      len = bad ? 0 : v + (kind == 0 ? 1u : mm) + ext;
+    }
+    const uint64_t lp = uint64_t(len) | (uint64_t(is0 ? len : 0u) << 32);
+    uint64_t ptot;
+    const uint64_t pex = block_excl_sum64(lp, &ptot, sh, 1);
+    const uint32_t cdst = dst + uint32_t(pex & 0xFFFFFFFFu), clit = litp + uint32_t(pex >> 32);
+    const uint32_t chunk_lit = uint32_t(ptot >> 32);
+    if (valid && uint64_t(cdst) + len > blen) bad = true;
+    if (is0 && uint64_t(clit) + len > n_lit) bad = true;
+    const uint64_t absdst = bs + cdst;
+    uint64_t src = 0;
+    Map4 mine = map_identity();
+    if (is1) {
+      src = sh.offval[k1_i];
+      if (src >= absdst) bad = true;
+      else mine = Map4{{absdst - src, kTagRef | 0, kTagRef | 1, kTagRef | 2}};
+    } else if (is2) {
+      const uint32_t r = (c >> 2) & 3;
+      mine.s[0] = kTagRef | r;
+      for (uint32_t k = 1; k <= 3; ++k) mine.s[k] = kTagRef | (k <= r ? k - 1 : k);
+    }
+    Map4 mtot;
+    const Map4 before = block_excl_map(mine, &mtot, sh);
+    if (is2) {
+      const uint32_t r = (c >> 2) & 3;
+      const uint64_t g = before.s[r];
+      const uint64_t d = (g & kTagRef) ? hist[g & 3] : g;
+      if (d > absdst) bad = true;
+      else src = absdst - d;
+    }
+    if ((is1 || is2) && !bad) {
+      const uint64_t gi = ntok + tok_i;
+      if (gi < tok_n) {
+        uint64_t* tk = a.tok + 2 * (tok_lo + gi);
+        tk[0] = src;
+        tk[1] = absdst | (uint64_t(len - 1) << 48);
+      } else {
+        bad = true;
+      }
+    }
+    // literal runs: starts in chunk literal space, and output literal bits
+    for (uint32_t w = t; w < B / 32; w += kParseThreads) sh.runbits[w] = 0;
+    __syncthreads();
+    if (is0 && !bad && len) {
+      const uint32_t j = clit - litp;
+      atomicOr(&sh.runbits[j >> 5], 1u << (j & 31));
+      sh.rundelta[run_i] = uint16_t(cdst - clit);
+      uint32_t p0 = cdst, p1 = cdst + len;
+      while (p0 < p1) {
+        const uint32_t w = p0 >> 5, lo = p0 & 31, hi = min(32u, lo + (p1 - p0));
+        const uint32_t mask = (hi == 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+        atomicOr(&sh.litbits[w], mask);
+        p0 += hi - lo;
+      }
+    }
+    if (__syncthreads_or(bad)) { failed = true; break; }
+    {  // run starts before each word of the chunk's literal space
+      const uint32_t nwords = (chunk_lit + 31) / 32;
+      uint32_t c2[2] = {0, 0};
+      for (uint32_t q = 0; q < 2; ++q) {
+        const uint32_t w = 2 * t + q;
+        c2[q] = w < nwords ? __popc(sh.runbits[w]) : 0;
+      }
+      uint64_t rt;
+      const uint64_t pre = block_excl_sum64(c2[0] + c2[1], &rt, sh, 0);
+      if (2 * t < nwords) sh.runpre[2 * t] = uint16_t(pre);
+      if (2 * t + 1 < nwords) sh.runpre[2 * t + 1] = uint16_t(pre + c2[0]);
+    }
+    __syncthreads();
+    for (uint32_t j = t; j < chunk_lit; j += kParseThreads) {  // place the chunk's literal bytes
+      const uint32_t w = j >> 5;
+      const uint32_t r = sh.runpre[w] + __popc(sh.runbits[w] & (0xFFFFFFFFu >> (31 - (j & 31)))) - 1;
+      sh.tile[litp + j + sh.rundelta[r]] = lit[litp + j];
+    }
+    __syncthreads();
+    dst += uint32_t(ptot & 0xFFFFFFFFu);
+    litp += chunk_lit;
+    ntok += n_tokc;
+    uint64_t nh[4];
+    for (int k = 0; k < 4; ++k) nh[k] = (mtot.s[k] & kTagRef) ? hist[mtot.s[k] & 3] : mtot.s[k];
+    for (int k = 0; k < 4; ++k) hist[k] = nh[k];
+  }
+  if (!failed && (dst != blen || litp != n_lit || lenc != n_len || offc != n_off || ntok != tok_n)) failed = true;
+  if (failed) {
+    if (t == 0) report(a.st, AX_E_CORRUPT, b);
+    return;
+  }
+  // write the tile (16-byte stores) and the block's readiness words
+  uint8_t* o = a.out + bs;
+  const uint32_t full = blen & ~15u;
+  for (uint32_t k = 16 * t; k < full; k += 16 * kParseThreads)
+    *reinterpret_cast<uint4*>(o + k) = *reinterpret_cast<const uint4*>(sh.tile + k);
+  for (uint32_t k = full + t; k < blen; k += kParseThreads) o[k] = sh.tile[k];
+  uint32_t* bw = a.bits + (item * (B / 32));
+  for (uint32_t w = t; w < (blen + 31) / 32; w += kParseThreads) bw[w] = sh.litbits[w];
+}
+
+// ----------------------------------------------------------------- k_copy --
+
+struct CopyArgs {
+  const uint64_t* tok;
+  uint64_t n_tok;
+  uint64_t win_lo;           // bytes below are final
+  uint8_t* out;
+  uint32_t* bits;            // window bitmap (bit 0 = byte win_lo)
+  DevStatus* st;
+  uint64_t n_chunks;
+  uint64_t spin_limit;
+  int serial;
+};
+
+__device__ inline bool source_ready(const uint32_t* bits, uint64_t win_lo, uint64_t s0, uint64_t s1) {
+  if (s1 <= win_lo) return true;
+  if (s0 < win_lo) s0 = win_lo;
+  s0 -= win_lo, s1 -= win_lo;
+  for (uint64_t w = s0 >> 5; w <= (s1 - 1) >> 5; ++w) {
+    const uint32_t lo = (w == (s0 >> 5)) ? uint32_t(s0 & 31) : 0u;
+    const uint32_t hi = (w == ((s1 - 1) >> 5)) ? uint32_t(((s1 - 1) & 31) + 1) : 32u;
+    const uint32_t mask = (hi == 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+    const uint32_t v = __hip_atomic_load(bits + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((v & mask) != mask) return false;
+  }
+  return true;
+}
+
+__device__ inline void mark_final(uint32_t* bits, uint64_t win_lo, uint64_t d0, uint64_t d1) {
+  d0 -= win_lo, d1 -= win_lo;
+  for (uint64_t w = d0 >> 5; w <= (d1 - 1) >> 5; ++w) {
+    const uint32_t lo = (w == (d0 >> 5)) ? uint32_t(d0 & 31) : 0u;
+    const uint32_t hi = (w == ((d1 - 1) >> 5)) ? uint32_t(((d1 - 1) & 31) + 1) : 32u;
+    const uint32_t mask = (hi == 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+    __hip_atomic_fetch_or(bits + w, mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// One lane copies a whole token, byte after byte, period-aware.
+__device__ inline void copy_lane(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len) {
+  const uint64_t dist = dst - src;
+  if (dist >= len) {
+    for (uint32_t k = 0; k < len; ++k) out[dst + k] = out[src + k];
+  } else {
+    uint32_t j = 0;
+    for (uint32_t k = 0; k < len; ++k) {
+      out[dst + k] = out[src + j];
+      if (++j == dist) j = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64 * kCopyWaves) void k_copy(CopyArgs a) {
+  const uint32_t lane = lane_id();
+  if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  for (;;) {
+    uint32_t chunk = 0;
+    if (lane == 0) chunk = atomicAdd(&a.st->ticket, 1u);
+    chunk = __shfl(chunk, 0, 64);
+    if (chunk >= a.n_chunks) break;
+    const uint64_t ti = uint64_t(chunk) * 64 + lane;
+    bool pending = ti < a.n_tok;
+    uint64_t src = 0, dst = 0;
+    uint32_t len = 0;
+    if (pending) {
+      src = a.tok[2 * ti];
+      const uint64_t w = a.tok[2 * ti + 1];
+      dst = w & ((1ull << 48) - 1);
+      len = uint32_t(w >> 48) + 1;
+    }
+    const uint64_t dist = dst - src;
+    const uint64_t s1 = src + (dist < len ? dist : len);
+    uint64_t spins = 0;
+    while (__ballot(pending)) {
+      const bool ready = pending && source_ready(a.bits, a.win_lo, src, s1);
+      const uint64_t rm = __ballot(ready);
+      if (rm) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (a.serial) {
+          if (ready) copy_lane(a.out, dst, src, len);
+        } else {
+          const bool lng = ready && len >= kLongToken;
+          if (ready && !lng) copy_lane(a.out, dst, src, len);
+          uint64_t lm = __ballot(lng);
+          while (lm) {  // long tokens: the whole wave fills them, period-aware
+            const int l = __builtin_ctzll(lm);
+            lm &= lm - 1;
+            const uint64_t d = __shfl((unsigned long long)dst, l, 64);
+            const uint64_t sr = __shfl((unsigned long long)src, l, 64);
+            const uint32_t n = __shfl(len, l, 64);
+            const uint64_t dd = d - sr;
+            if (dd >= n) {
+              for (uint32_t k = lane; k < n; k += 64) a.out[d + k] = a.out[sr + k];
+            } else {
+              const uint32_t step = uint32_t(64 % dd);
+              uint32_t j = uint32_t(lane % dd);
+              for (uint32_t k = lane; k < n; k += 64) {
+                a.out[d + k] = a.out[sr + j];
+                j += step;
+                if (j >= dd) j -= uint32_t(dd);
+              }
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (ready) mark_final(a.bits, a.win_lo, dst, dst + len);
+        pending = pending && !ready;
+      } else {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > a.spin_limit ||
+            ((spins & 63) == 0 && __hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+          if (lane == 0 && spins > a.spin_limit) report(a.st, AX_E_DEVICE, ~0ull);
+          return;
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_init(DevStatus* st) {
+  if (threadIdx.x == 0) {
+    st->err = 0;
+    st->bad_block = ~0ull;
+    st->ticket = 0;
+  }
+}
+
+__global__ void k_reset_ticket(DevStatus* st) {
+  if (threadIdx.x == 0) st->ticket = 0;
+}
+
+// --------------------------------------------------------------- host side --
+
+inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+
+struct Layout {
+  uint64_t status, nsym, lit, cmd, off, len, tok, bits, total;
+};
+
+}  // namespace
+
+struct aceapex_decoder {
+  aceapex_info info{};
+  std::vector<uint64_t> offs, mpre;
+  const uint8_t* d_arc = nullptr;
+  uint64_t arc_len = 0;
+  uint32_t window_blocks = 0;  // blocks per decode window
+  uint64_t window_tok_max = 0; // most tokens in any window
+  uint32_t off_cap = 0, len_cap = 0;
+  int copy_grid = 0;
+  bool timing = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool events_ok = false;
+  Layout lay{};
+};
+
+namespace {
+
+Layout make_layout(const aceapex_decoder& d) {
+  Layout L{};
+  const uint64_t W = d.window_blocks, B = d.info.block_size;
+  uint64_t at = 0;
+  L.status = at, at = align256(at + sizeof(DevStatus));
+  L.nsym = at, at = align256(at + 16 * W);
+  L.lit = at, at = align256(at + W * B);
+  L.cmd = at, at = align256(at + W * B);
+  L.off = at, at = align256(at + W * d.off_cap);
+  L.len = at, at = align256(at + W * d.len_cap);
+  L.tok = at, at = align256(at + 16 * std::max<uint64_t>(1, d.window_tok_max));
+  L.bits = at, at = align256(at + W * (B / 8));
+  L.total = at;
+  return L;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  (void)what;
+  return ax::fail(AX_E_HIP, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+int aceapex_read_info(const uint8_t* h, uint64_t len, aceapex_info* info) {
+  if (!h || !info || len < 64) return ax::fail(AX_E_ARG, "need at least the 64-byte header");
+  if (ax::get32(h) != ax::kMagic || ax::get16(h + 4) != 1) return ax::fail(AX_E_CORRUPT, "bad magic or version");
+  aceapex_info I{};
+  I.flags = ax::get16(h + 6);
+  I.block_size = ax::get32(h + 8);
+  I.min_match = ax::get16(h + 12);
+  I.depth_cap = ax::get16(h + 14);
+  I.n_bytes = ax::get64(h + 16);
+  I.n_blocks = ax::get64(h + 24);
+  I.xxh3 = ax::get64(h + 32);
+  I.payload_bytes = ax::get64(h + 40);
+  I.n_matches = ax::get64(h + 48);
+  const uint32_t B = I.block_size;
+  if (B < 4096 || B > 65536 || (B & (B - 1)) || I.min_match < 1 || I.min_match > 255)
+    return ax::fail(AX_E_CORRUPT, "bad block size or min_match");
+  if (I.n_blocks != (I.n_bytes + B - 1) / B) return ax::fail(AX_E_CORRUPT, "block count mismatch");
+  if (I.n_blocks > (1ull << 40)) return ax::fail(AX_E_CORRUPT, "block count too large");
+  I.header_bytes = 64 + 16 * (I.n_blocks + 1);
+  I.archive_bytes = I.header_bytes + I.payload_bytes;
+  if (I.archive_bytes < I.header_bytes) return ax::fail(AX_E_CORRUPT, "size overflow");
+  *info = I;
+  return AX_OK;
+}
+
+int aceapex_decoder_create(const uint8_t* h, uint64_t h_len, const uint8_t* d_arc, uint64_t arc_len,
+                           aceapex_decoder** out) {
+  if (!out) return ax::fail(AX_E_ARG, "null out");
+  *out = nullptr;
+  aceapex_info I;
+  int rc = aceapex_read_info(h, h_len, &I);
+  if (rc) return rc;
+  if (h_len < I.header_bytes) return ax::fail(AX_E_ARG, "host copy shorter than header + index");
+  if (!d_arc || arc_len < I.archive_bytes) return ax::fail(AX_E_ARG, "device archive shorter than the header says");
+  if (I.block_size > kMaxB) return ax::fail(AX_E_UNSUPPORTED, "device decoder takes blocks up to 16384 bytes");
+  aceapex_decoder* d = new (std::nothrow) aceapex_decoder;
+  if (!d) return ax::fail(AX_E_NOMEM, "decoder handle");
+  d->info = I;
+  d->d_arc = d_arc;
+  d->arc_len = arc_len;
+  const uint64_t nb = I.n_blocks, B = I.block_size;
+  try {
+    d->offs.resize(nb + 1);
+    d->mpre.resize(nb + 1);
+  } catch (const std::bad_alloc&) {
+    delete d;
+    return ax::fail(AX_E_NOMEM, "index copy");
+  }
+  const uint8_t* ix = h + 64;
+  for (uint64_t b = 0; b <= nb; ++b) d->offs[b] = ax::get64(ix + 8 * b), d->mpre[b] = ax::get64(ix + 8 * (nb + 1) + 8 * b);
+  bool ok = d->offs[0] == 0 && d->offs[nb] == I.payload_bytes && d->mpre[0] == 0 && d->mpre[nb] == I.n_matches;
+  const uint64_t max_tok = B / I.min_match;
+  for (uint64_t b = 0; b < nb && ok; ++b) {
+    ok &= d->offs[b + 1] >= d->offs[b] + 16 && ((d->offs[b + 1] - d->offs[b]) & 15) == 0;
+    ok &= d->mpre[b + 1] >= d->mpre[b] && d->mpre[b + 1] - d->mpre[b] <= max_tok;
+  }
+  if (!ok) {
+    delete d;
+    return ax::fail(AX_E_CORRUPT, "bad index");
+  }
+  d->off_cap = uint32_t((10 * (B / I.min_match + 1) + 15) & ~15u);
+  d->len_cap = uint32_t(3 * B);
+  // windows of up to 32768 blocks bound the workspace for very large archives
+  d->window_blocks = uint32_t(std::min<uint64_t>(std::max<uint64_t>(nb, 1), 32768));
+  for (uint64_t b0 = 0; b0 < nb; b0 += d->window_blocks) {
+    const uint64_t b1 = std::min<uint64_t>(nb, b0 + d->window_blocks);
+    d->window_tok_max = std::max(d->window_tok_max, d->mpre[b1] - d->mpre[b0]);
+  }
+  d->lay = make_layout(*d);
+  int dev = 0, cus = 0, occ = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_copy), 64 * kCopyWaves, 0);
+  d->copy_grid = std::max(1, cus) * std::max(1, occ);
+  *out = d;
+  return AX_OK;
+}
+
+void aceapex_decoder_destroy(aceapex_decoder* d) {
+  if (!d) return;
+  for (auto& e : d->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete d;
+}
+
+int aceapex_decoder_info(const aceapex_decoder* d, aceapex_info* info) {
+  if (!d || !info) return ax::fail(AX_E_ARG, "null argument");
+  *info = d->info;
+  return AX_OK;
+}
+
+int aceapex_decoder_workspace(const aceapex_decoder* d, uint64_t* bytes) {
+  if (!d || !bytes) return ax::fail(AX_E_ARG, "null argument");
+  *bytes = d->lay.total;
+  return AX_OK;
+}
+
+int aceapex_decoder_set_timing(aceapex_decoder* d, int enable) {
+  if (!d) return ax::fail(AX_E_ARG, "null decoder");
+  if (enable && !d->events_ok) {
+    for (auto& e : d->ev) {
+      hipError_t er = hipEventCreate(&e);
+      if (er != hipSuccess) return hip_fail(er, "hipEventCreate");
+    }
+    d->events_ok = true;
+  }
+  d->timing = enable != 0;
+  return AX_OK;
+}
+
+int aceapex_decoder_stage_ms(aceapex_decoder* d, float* ans, float* parse, float* copy) {
+  if (!d || !ans || !parse || !copy) return ax::fail(AX_E_ARG, "null argument");
+  if (!d->events_ok) return ax::fail(AX_E_ARG, "timing not enabled");
+  hipError_t e = hipEventSynchronize(d->ev[3]);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  (void)hipEventElapsedTime(ans, d->ev[0], d->ev[1]);
+  (void)hipEventElapsedTime(parse, d->ev[1], d->ev[2]);
+  (void)hipEventElapsedTime(copy, d->ev[2], d->ev[3]);
+  return AX_OK;
+}
+
+int aceapex_decode_all(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, void* d_work, uint64_t work_len,
+                       int copy_mode, void* stream) {
+  if (!d || (!d_out && d->info.n_bytes) || !d_work) return ax::fail(AX_E_ARG, "null argument");
+  if (out_cap < d->info.n_bytes) return ax::fail(AX_E_CAPACITY, "output smaller than the decoded size");
+  if (work_len < d->lay.total) return ax::fail(AX_E_CAPACITY, "workspace too small");
+  if ((reinterpret_cast<uintptr_t>(d_work) & 255) || (reinterpret_cast<uintptr_t>(d_out) & 15))
+    return ax::fail(AX_E_ARG, "workspace must be 256-byte and output 16-byte aligned");
+  if (copy_mode != AX_COPY_PERIODIC && copy_mode != AX_COPY_SERIAL) return ax::fail(AX_E_ARG, "bad copy mode");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint8_t* w = static_cast<uint8_t*>(d_work);
+  const Layout& L = d->lay;
+  DevStatus* st = reinterpret_cast<DevStatus*>(w + L.status);
+  const aceapex_info& I = d->info;
+  const uint64_t nb = I.n_blocks, B = I.block_size;
+  const bool timed = d->timing && d->events_ok;
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, st);
+  for (uint64_t b0 = 0; b0 < nb; b0 += d->window_blocks) {
+    const uint32_t items = uint32_t(std::min<uint64_t>(nb - b0, d->window_blocks));
+    const bool first = b0 == 0, last = b0 + items == nb;
+    AnsArgs aa{d->d_arc, I.header_bytes, b0, items, uint32_t(B), w + L.lit, w + L.cmd, w + L.off, w + L.len,
+               d->off_cap, d->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
+    if (timed && first) (void)hipEventRecord(d->ev[0], s);
+    hipLaunchKernelGGL(k_ans, dim3(4 * items), dim3(64), 0, s, aa);
+    if (timed && first) (void)hipEventRecord(d->ev[1], s);
+    const uint64_t t0 = d->mpre[b0], t1 = d->mpre[b0 + items];
+    ParseArgs pa{d->d_arc, I.n_bytes, b0, items, uint32_t(B), I.min_match, w + L.lit, w + L.cmd, w + L.off,
+                 w + L.len, d->off_cap, d->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), t0, t1 - t0,
+                 reinterpret_cast<uint64_t*>(w + L.tok), d_out, reinterpret_cast<uint32_t*>(w + L.bits), st};
+    hipLaunchKernelGGL(k_parse, dim3(items), dim3(kParseThreads), 0, s, pa);
+    if (timed && first) (void)hipEventRecord(d->ev[2], s);
+    if (!first) hipLaunchKernelGGL(k_reset_ticket, dim3(1), dim3(64), 0, s, st);
+    const uint64_t ntok = t1 - t0, chunks = (ntok + 63) / 64;
+    if (chunks) {
+      CopyArgs ca{reinterpret_cast<const uint64_t*>(w + L.tok), ntok, b0 * B, d_out,
+                  reinterpret_cast<uint32_t*>(w + L.bits), st, chunks, 1ull << 22, copy_mode == AX_COPY_SERIAL};
+      const uint64_t waves_needed = chunks, wg_needed = (waves_needed + kCopyWaves - 1) / kCopyWaves;
+      const uint32_t grid = uint32_t(std::min<uint64_t>(wg_needed, uint64_t(d->copy_grid)));
+      hipLaunchKernelGGL(k_copy, dim3(grid), dim3(64 * kCopyWaves), 0, s, ca);
+    }
+    if (timed && last) (void)hipEventRecord(d->ev[3], s);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return AX_OK;
+}
+
+int aceapex_decoder_status(aceapex_decoder* d, void* d_work, void* stream, int32_t* dev_err, uint64_t* bad_block) {
+  if (!d || !d_work || !dev_err || !bad_block) return ax::fail(AX_E_ARG, "null argument");
+  DevStatus hs;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&hs, static_cast<uint8_t*>(d_work) + d->lay.status, sizeof(hs), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "status read");
+  *dev_err = hs.err;
+  *bad_block = hs.bad_block;
+  return AX_OK;
+}
+
+}  // extern "C"
