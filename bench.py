@@ -1,0 +1,174 @@
+"""Benchmark: device-resident full decode of the 254 MB synthetic DNA archive.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dna254|text200|dna4]
+                [--copy periodic|serial] [--no-rep] [--no-cpu-baseline]
+
+One step = one aceapex_decode_all of the whole archive (rANS of the four
+streams of every block, command parse with literal placement, match copy with
+periodic fills scheduled by source readiness), inputs resident in HBM.
+Prints one JSON line.  The archive is generated and encoded on the host first
+(outside the timed region); the decode is checked byte for byte against the
+original before timing.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded GB/s device-resident (254 MB DNA) vs HBM peak; p50/p99 us per 16 KB read"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (generator, bytes, seed, description)
+    "dna254": ("dna", 15500 * 16384, 2, "synthetic DNA 253,952,000 B, 15,500 x 16 KiB blocks"),
+    "text200": ("text", 209715200, 3, "synthetic English-like text 209,715,200 B, 12,800 x 16 KiB blocks"),
+    "dna4": ("dna", 4 * 1024 * 1024, 1, "synthetic DNA 4 MiB, 256 x 16 KiB blocks"),
+}
+
+
+def parse_args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dna254", choices=sorted(WORKLOADS))
+    ap.add_argument("--copy", default="periodic", choices=["periodic", "serial"])
+    ap.add_argument("--no-rep", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--threads", type=int, default=0, help="encoder threads (0 = all)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(arc, n_bytes):
+    """The oracle's sequential decode on one host core, over the whole archive
+    (a bounded ~3-10 s of CPU work at this size)."""
+    import oracle
+
+    times = []
+    for _ in range(3):
+        t = time.perf_counter()
+        oracle.decode(arc, verify=False)
+        times.append(time.perf_counter() - t)
+    t = float(np.median(times))
+    return {"value": n_bytes / t / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole archive ({n_bytes} B), median of 3 single-threaded oracle decodes, {t:.2f} s each"}
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import xxhash
+
+    import synth
+    import paper_2608_10188_amd as ax
+
+    gen, n, seed, desc = WORKLOADS[args.workload]
+    t0 = time.time()
+    x = synth.dna(n, seed) if gen == "dna" else synth.text(n, seed)
+    log(f"generated {n} B in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    arc, st = ax.encode(x, stats=True, no_rep=int(args.no_rep), threads=args.threads)
+    log(f"encoded to {arc.size} B (ratio {n / arc.size:.3f}) in {time.time() - t0:.1f}s; "
+        f"{st.n_commands} commands, {st.n_matches} matches, {st.n_rep} repeats")
+    want = xxhash.xxh3_64_intdigest(x.tobytes())
+
+    dev = torch.device("cuda:0")
+    d_arc = torch.from_numpy(arc).to(dev)
+    dec = ax.Decoder(arc, d_arc)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    work = dec.workspace()
+    mode = ax.COPY_SERIAL if args.copy == "serial" else ax.COPY_PERIODIC
+    stream = torch.cuda.current_stream()
+
+    # correctness first (poisoned output), outside the timed region
+    out.fill_(0xCC)
+    dec.decode_all(out=out, copy_mode=mode)
+    err, bad = dec.status()
+    got = out.cpu().numpy()
+    ok = err == 0 and xxhash.xxh3_64_intdigest(got.tobytes()) == want and np.array_equal(got, x)
+    if not ok:
+        log(f"DECODE MISMATCH err={err} block={bad}")
+        print(json.dumps({"metric": METRIC, "value": None, "error": "decode mismatch"}))
+        sys.exit(1)
+    del got
+
+    dec.set_timing(True)
+    for _ in range(args.warmup):
+        dec.decode_all(out=out, copy_mode=mode)
+    torch.cuda.synchronize()
+    stage = np.zeros(3)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        dec.decode_all(out=out, copy_mode=mode)
+        stage += np.array(dec.stage_ms())  # blocks on this step's last event
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    gpu_ms = ev0.elapsed_time(ev1)
+    err, bad = dec.status()
+    if err:
+        log(f"device status {err} during timing")
+        sys.exit(1)
+    ms_per_step = gpu_ms / args.steps
+    value = n / (ms_per_step / 1e3) / 1e9
+    ans_ms, parse_ms, copy_ms = (stage / args.steps).tolist()
+
+    # algorithmic bytes per decode: output N, compressed archive C, match
+    # source bytes S = sum over matches of min(len, dist)
+    s_bytes = int(st.n_src_bytes)
+    match_bytes = int(st.n_match_bytes)
+    c_bytes = int(arc.size)
+    b_alg = n + c_bytes + s_bytes
+    d_bytes = int(st.n_lit_bytes + st.n_commands + st.n_off_bytes + st.n_len_bytes)  # decoded stream symbols
+
+    stages = {"ans": ans_ms, "parse": parse_ms, "copy": copy_ms}
+    dom = max(stages, key=stages.get)
+    # per-kernel algorithmic bytes (stated in the design notes):
+    #   ans:   read compressed payload C, write decoded stream symbols D
+    #   parse: read decoded symbols D, write the output N (tile) and tokens
+    #   copy:  read match sources S, write match bytes M
+    alg = {"ans": c_bytes + d_bytes, "parse": d_bytes + n + 16 * st.n_matches, "copy": s_bytes + match_bytes}
+    achieved = alg[dom] / (stages[dom] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": f"k_{dom}",
+                "pipeline_alg_bytes": b_alg,
+                "pipeline_frac": round(b_alg / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 5)}
+
+    res = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": desc, "n_bytes": n, "archive_bytes": c_bytes,
+                   "ratio": round(n / c_bytes, 4), "blocks": int(dec.info.n_blocks),
+                   "commands": int(st.n_commands), "matches": int(st.n_matches), "repeats": int(st.n_rep),
+                   "copy_mode": args.copy, "no_rep": bool(args.no_rep)},
+        "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 5),
+        "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+        "stage_share": {k: round(v / max(1e-9, sum(stages.values())), 4) for k, v in stages.items()},
+        "wall_s": round(wall, 3),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(arc, n)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,8 +75,12 @@ typedef struct {
   uint32_t rans_min_syms_per_lane, off_cost, window_log, threads;
 } aceapex_encode_params;
 
+/* Encoder statistics.  n_src_bytes = sum over matches of min(len, dist): the
+ * source bytes a periodic-fill copy reads.  n_off_bytes / n_len_bytes are the
+ * decoded sizes of the offset and length streams. */
 typedef struct {
   uint64_t n_bytes, n_blocks, comp_bytes, n_commands, n_matches, n_rep, n_match_bytes, n_lit_bytes;
+  uint64_t n_src_bytes, n_off_bytes, n_len_bytes;
   uint32_t max_depth, passes;
 } aceapex_encode_stats;
 
@@ -145,6 +149,13 @@ int aceapex_decode_all(aceapex_decoder* dec, uint8_t* d_out, uint64_t out_cap, v
 int aceapex_decoder_stage_ms(aceapex_decoder* dec, float* ans_ms, float* parse_ms, float* copy_ms);
 /* 1 = record stage events on later decodes (adds three event records). */
 int aceapex_decoder_set_timing(aceapex_decoder* dec, int enable);
+
+/* Decoder options (schedule knobs; none changes a decoded byte).
+ *   AX_OPT_BULK_ROUNDS  number of level-synchronous match-layer rounds (one
+ *     launch each, plain cached accesses) before the persistent launch that
+ *     finishes the deeper tokens, in [1, 250] (default 4). */
+enum { AX_OPT_BULK_ROUNDS = 1 };
+int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
 
 /* Read the device status word of a workspace after the work queued on
  * `stream`: synchronises `stream`.  *dev_err is 0 or an AX_E_* code;

@@ -22,8 +22,9 @@ EXPORTS = [
     "aceapex_strerror", "aceapex_last_error", "aceapex_encode_params_default", "aceapex_encode_bound",
     "aceapex_encode", "aceapex_read_info", "aceapex_decoder_create", "aceapex_decoder_destroy",
     "aceapex_decoder_info", "aceapex_decoder_workspace", "aceapex_decode_all", "aceapex_decoder_stage_ms",
-    "aceapex_decoder_set_timing", "aceapex_decoder_status",
+    "aceapex_decoder_set_timing", "aceapex_decoder_status", "aceapex_decoder_set_option",
 ]
+OPT_BULK_ROUNDS = 1
 
 
 class AceapexError(RuntimeError):
@@ -43,7 +44,8 @@ class EncodeParams(ctypes.Structure):
 class EncodeStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "n_bytes", "n_blocks", "comp_bytes", "n_commands", "n_matches", "n_rep", "n_match_bytes",
-        "n_lit_bytes")] + [("max_depth", ctypes.c_uint32), ("passes", ctypes.c_uint32)]
+        "n_lit_bytes", "n_src_bytes", "n_off_bytes", "n_len_bytes")] + [
+        ("max_depth", ctypes.c_uint32), ("passes", ctypes.c_uint32)]
 
 
 class Info(ctypes.Structure):
@@ -79,6 +81,7 @@ def _load():
     L.aceapex_decoder_stage_ms.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float)]
     L.aceapex_decoder_set_timing.argtypes = [vp, ctypes.c_int]
     L.aceapex_decoder_status.argtypes = [vp, vp, vp, P(ctypes.c_int32), P(u64)]
+    L.aceapex_decoder_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
     _lib = L
     return L
 
@@ -172,6 +175,12 @@ class Decoder:
         if self._work is None:
             self._work = torch.empty(max(256, self.workspace_bytes), dtype=torch.uint8, device=self.device)
         return self._work
+
+    def set_option(self, option, value):
+        _check(_load().aceapex_decoder_set_option(self._h, int(option), int(value)), "set_option")
+
+    def set_bulk_rounds(self, rounds):
+        self.set_option(OPT_BULK_ROUNDS, rounds)
 
     def set_timing(self, on=True):
         _check(_load().aceapex_decoder_set_timing(self._h, int(bool(on))), "set_timing")

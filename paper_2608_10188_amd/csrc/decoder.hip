@@ -12,14 +12,18 @@
 //            history (each command is a map on history tuples); literal runs
 //            are placed into an LDS tile that is written out with 16-byte
 //            stores; matches become tokens (src, dst, len).
-//   k_copy   the match layer: waves take chunks of 64 tokens in output order
-//            from a ticket counter and copy every token whose source bytes
-//            are final (a readiness bitmap, one bit per output byte), as a
-//            periodic fill out[dst+k] = out[src + k mod dist]
-//            (periodic-fill section); long tokens are copied by the whole
-//            wave.  A token only waits on bytes below its own destination,
-//            written by literals or by tokens with lower tickets, so the
-//            schedule follows the dependency levels without a level plan.
+//   match layer: every token (src, dst, len) is written as a periodic fill
+//            out[dst+k] = out[src + k mod dist] (periodic-fill section).  The
+//            tokens whose destinations meet a token's source bytes form one
+//            contiguous index range (tokens are stored in output order), found
+//            once by binary search; a token is ready when those are done.
+//            k_round runs level-synchronous rounds (the dependency levels of
+//            the paper's wavefront decoder) with plain cached accesses, the
+//            kernel boundary being the only synchronisation; k_tail then
+//            finishes the deep remainder in one persistent launch, waves
+//            taking 64-token chunks in output order from a ticket counter and
+//            publishing through agent-coherent stores, so a dependency hop
+//            costs a memory round trip rather than an L2 writeback.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,8 +38,9 @@ namespace {
 
 constexpr uint32_t kMaxB = 16384;           // largest block the device path decodes
 constexpr uint32_t kParseThreads = 256;
-constexpr uint32_t kCopyWaves = 4;          // waves per k_copy workgroup
-constexpr uint32_t kLongToken = 48;         // tokens at least this long are copied by the whole wave
+constexpr uint32_t kCopyThreads = 256;      // match-layer workgroup
+constexpr uint32_t kLongToken = 64;         // tokens at least this long are copied by the whole wave
+constexpr uint8_t kPending = 0xFF;          // done[] value of a token not yet copied
 constexpr uint64_t kTagRef = 1ull << 63;    // history-map slot holding an input index
 
 struct DevStatus {
@@ -43,7 +48,8 @@ struct DevStatus {
   uint32_t pad0;
   unsigned long long bad_block;
   uint32_t ticket;
-  uint32_t pad1[59];
+  uint32_t count[3];  // pending-list lengths of the level-synchronous rounds
+  uint32_t pad1[56];
 };
 static_assert(sizeof(DevStatus) == 256, "status block is 256 bytes");
 
@@ -267,8 +273,8 @@ struct ParseArgs {
   uint64_t tok_first;        // cumulative match count at the window start
   uint64_t tok_count;        // tokens in the window
   uint64_t* tok;             // 2 u64 per token: src, dst | (len-1) << 48
+  uint8_t* done;             // per token: kPending until the match layer copies it
   uint8_t* out;              // decoded bytes (absolute positions)
-  uint32_t* bits;            // readiness bitmap of the window, 1 bit per byte
   DevStatus* st;
 };
 
@@ -304,7 +310,6 @@ __device__ inline Map4 map_shfl(const Map4& m, int src) {
 
 struct ParseShared {
   uint8_t tile[kMaxB];
-  uint32_t litbits[kMaxB / 32];   // literal bytes of the block (output space)
   uint32_t runbits[kMaxB / 32];   // run starts in the chunk's literal space
   uint16_t runpre[kMaxB / 32];    // run starts in earlier words
   uint16_t rundelta[kParseThreads];
@@ -445,7 +450,6 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
   const uint64_t* mpre = reinterpret_cast<const uint64_t*>(a.arc + 64) + (a.n_bytes + B - 1) / B + 1;
   const uint64_t tok_lo = mpre[b] - a.tok_first, tok_n = mpre[b + 1] - mpre[b];
 
-  for (uint32_t w = t; w < B / 32; w += kParseThreads) sh.litbits[w] = 0;
   if (t == 0) sh.bad = (n_lit > B || n_cmd > B || n_len > a.len_cap || n_off > a.off_cap) ? 1 : 0;
   __syncthreads();
   bool failed = sh.bad != 0;
@@ -518,24 +522,18 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
         uint64_t* tk = a.tok + 2 * (tok_lo + gi);
         tk[0] = src;
         tk[1] = absdst | (uint64_t(len - 1) << 48);
+        a.done[tok_lo + gi] = kPending;
       } else {
         bad = true;
       }
     }
-    // literal runs: starts in chunk literal space, and output literal bits
+    // literal runs: starts in the chunk's literal space
     for (uint32_t w = t; w < B / 32; w += kParseThreads) sh.runbits[w] = 0;
     __syncthreads();
     if (is0 && !bad && len) {
       const uint32_t j = clit - litp;
       atomicOr(&sh.runbits[j >> 5], 1u << (j & 31));
       sh.rundelta[run_i] = uint16_t(cdst - clit);
-      uint32_t p0 = cdst, p1 = cdst + len;
-      while (p0 < p1) {
-        const uint32_t w = p0 >> 5, lo = p0 & 31, hi = min(32u, lo + (p1 - p0));
-        const uint32_t mask = (hi == 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
-        atomicOr(&sh.litbits[w], mask);
-        p0 += hi - lo;
-      }
     }
     if (__syncthreads_or(bad)) { failed = true; break; }
     {  // run starts before each word of the chunk's literal space
@@ -569,69 +567,199 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     if (t == 0) report(a.st, AX_E_CORRUPT, b);
     return;
   }
-  // write the tile (16-byte stores) and the block's readiness words
+  // write the tile with 16-byte stores (match bytes are filled by the match layer)
   uint8_t* o = a.out + bs;
   const uint32_t full = blen & ~15u;
   for (uint32_t k = 16 * t; k < full; k += 16 * kParseThreads)
     *reinterpret_cast<uint4*>(o + k) = *reinterpret_cast<const uint4*>(sh.tile + k);
   for (uint32_t k = full + t; k < blen; k += kParseThreads) o[k] = sh.tile[k];
-  uint32_t* bw = a.bits + (item * (B / 32));
-  for (uint32_t w = t; w < (blen + 31) / 32; w += kParseThreads) bw[w] = sh.litbits[w];
 }
 
-// ----------------------------------------------------------------- k_copy --
+// ------------------------------------------------------------ match layer --
 
 struct CopyArgs {
-  const uint64_t* tok;
-  uint64_t n_tok;
+  const uint64_t* tok;       // window tokens in output order
+  uint32_t n_tok;
   uint64_t win_lo;           // bytes below are final
   uint8_t* out;
-  uint32_t* bits;            // window bitmap (bit 0 = byte win_lo)
+  uint32_t* cov;             // per token: first covering token, count
+  uint8_t* done;             // per token: round that copied it, or kPending
+  const uint32_t* list_in;   // pending tokens of the previous round
+  uint32_t* list_out;
+  const uint32_t* cnt_in;
+  uint32_t* cnt_out;
+  uint32_t* cnt_clear;       // the counter the next round writes
+  uint32_t round;
   DevStatus* st;
-  uint64_t n_chunks;
+  uint32_t n_chunks;
   uint64_t spin_limit;
   int serial;
 };
 
-__device__ inline bool source_ready(const uint32_t* bits, uint64_t win_lo, uint64_t s0, uint64_t s1) {
-  if (s1 <= win_lo) return true;
-  if (s0 < win_lo) s0 = win_lo;
-  s0 -= win_lo, s1 -= win_lo;
-  for (uint64_t w = s0 >> 5; w <= (s1 - 1) >> 5; ++w) {
-    const uint32_t lo = (w == (s0 >> 5)) ? uint32_t(s0 & 31) : 0u;
-    const uint32_t hi = (w == ((s1 - 1) >> 5)) ? uint32_t(((s1 - 1) & 31) + 1) : 32u;
-    const uint32_t mask = (hi == 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
-    const uint32_t v = __hip_atomic_load(bits + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((v & mask) != mask) return false;
-  }
-  return true;
+__device__ inline void token_at(const uint64_t* tok, uint64_t t, uint64_t& src, uint64_t& dst, uint32_t& len) {
+  src = tok[2 * t];
+  const uint64_t w = tok[2 * t + 1];
+  dst = w & ((1ull << 48) - 1);
+  len = uint32_t(w >> 48) + 1;
 }
 
-__device__ inline void mark_final(uint32_t* bits, uint64_t win_lo, uint64_t d0, uint64_t d1) {
-  d0 -= win_lo, d1 -= win_lo;
-  for (uint64_t w = d0 >> 5; w <= (d1 - 1) >> 5; ++w) {
-    const uint32_t lo = (w == (d0 >> 5)) ? uint32_t(d0 & 31) : 0u;
-    const uint32_t hi = (w == ((d1 - 1) >> 5)) ? uint32_t(((d1 - 1) & 31) + 1) : 32u;
-    const uint32_t mask = (hi == 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
-    __hip_atomic_fetch_or(bits + w, mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Tokens [lo, lo+cnt) are those whose destinations meet [s0, s1); tokens are
+// disjoint and sorted by destination.
+__device__ inline void find_cover(const uint64_t* tok, uint32_t n, uint64_t s0, uint64_t s1, uint32_t& lo,
+                                  uint32_t& cnt) {
+  uint32_t a = 0, b = n;
+  while (a < b) {  // first token ending after s0
+    const uint32_t mid = (a + b) >> 1;
+    const uint64_t w = tok[2 * uint64_t(mid) + 1];
+    if ((w & ((1ull << 48) - 1)) + (w >> 48) + 1 <= s0) a = mid + 1; else b = mid;
   }
+  lo = a;
+  cnt = 0;
+  while (a + cnt < n && (tok[2 * uint64_t(a + cnt) + 1] & ((1ull << 48) - 1)) < s1) ++cnt;
 }
 
-// One lane copies a whole token, byte after byte, period-aware.
-__device__ inline void copy_lane(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len) {
+template <bool COH>
+__device__ inline uint8_t ldb(const uint8_t* p) {
+  if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool COH>
+__device__ inline void stb(uint8_t* p, uint8_t v) {
+  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
+// One lane fills a token as a periodic fill: sixteen source loads in flight,
+// then sixteen stores.  The source index runs over the period dist (for
+// dist >= len it never wraps and the fill is a plain copy).
+template <bool COH>
+__device__ inline void fill_lane(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len) {
   const uint64_t dist = dst - src;
-  if (dist >= len) {
-    for (uint32_t k = 0; k < len; ++k) out[dst + k] = out[src + k];
-  } else {
-    uint32_t j = 0;
-    for (uint32_t k = 0; k < len; ++k) {
-      out[dst + k] = out[src + j];
+  uint64_t j = 0;
+  for (uint32_t k0 = 0; k0 < len; k0 += 16) {
+    uint64_t idx[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      idx[q] = j;
       if (++j == dist) j = 0;
+    }
+    uint8_t v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = (k0 + q < len) ? ldb<COH>(out + src + idx[q]) : uint8_t(0);
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (k0 + q < len) stb<COH>(out + dst + k0 + q, v[q]);
+  }
+}
+
+// The serial ablation: one lane, byte after byte, reading the bytes it may
+// itself have just written (a self-overlapping match is a dependency chain).
+template <bool COH>
+__device__ inline void fill_serial(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len) {
+  for (uint32_t k = 0; k < len; ++k) {
+    stb<COH>(out + dst + k, ldb<COH>(out + src + k));
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // the next load may read this byte
+  }
+}
+
+// The whole wave fills one long token: four bytes per lane in flight.
+template <bool COH>
+__device__ inline void fill_wave(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len, uint32_t lane) {
+  const uint64_t dist = dst - src;
+  const uint64_t step = 64 % dist;
+  uint64_t j = lane % dist;
+  for (uint32_t k0 = lane; k0 < len; k0 += 256) {
+    uint64_t idx[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      idx[q] = j;
+      j += step;
+      if (j >= dist) j -= dist;
+    }
+    uint8_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = (k0 + 64 * q < len) ? ldb<COH>(out + src + idx[q]) : uint8_t(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k0 + 64 * q < len) stb<COH>(out + dst + k0 + 64 * q, v[q]);
+  }
+}
+
+// Copy this wave's ready tokens: short ones lane by lane, long ones by the
+// whole wave.
+template <bool COH>
+__device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64_t src, uint32_t len, int serial) {
+  const uint32_t lane = lane_id();
+  if (serial) {
+    if (ready) fill_serial<COH>(out, dst, src, len);
+    return;
+  }
+  const bool lng = ready && len >= kLongToken;
+  if (ready && !lng) fill_lane<COH>(out, dst, src, len);
+  uint64_t lm = __ballot(lng);
+  while (lm) {
+    const int l = __builtin_ctzll(lm);
+    lm &= lm - 1;
+    const uint64_t d = __shfl((unsigned long long)dst, l, 64);
+    const uint64_t sr = __shfl((unsigned long long)src, l, 64);
+    const uint32_t n = __shfl(len, l, 64);
+    fill_wave<COH>(out, d, sr, n, lane);
+  }
+}
+
+// Level-synchronous round r.  Round 0 visits every token, records its
+// covering range and copies the tokens whose sources are all literal bytes
+// (or lie before the window); later rounds visit the previous round's
+// leftovers.  A token copied in round r marks done = r; a token is ready in
+// round r only if its covering tokens are marked < r, i.e. were copied by an
+// earlier launch, so no access within a round races.
+template <bool FIRST>
+__global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
+  if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  const uint32_t lane = lane_id();
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_clear = 0;
+  const uint32_t n_items = FIRST ? a.n_tok : *a.cnt_in;
+  for (uint64_t base = uint64_t(blockIdx.x) * kCopyThreads; base < n_items; base += uint64_t(gridDim.x) * kCopyThreads) {
+    const uint64_t item = base + threadIdx.x;
+    const bool act = item < n_items;
+    const uint32_t t = act ? (FIRST ? uint32_t(item) : a.list_in[item]) : 0u;
+    uint64_t src = 0, dst = 0;
+    uint32_t len = 0, lo = 0, cnt = 0;
+    if (act) {
+      token_at(a.tok, t, src, dst, len);
+      if (FIRST) {
+        const uint64_t dist = dst - src;
+        const uint64_t s1 = src + (dist < len ? dist : len);
+        if (s1 > a.win_lo) find_cover(a.tok, a.n_tok, src < a.win_lo ? a.win_lo : src, s1, lo, cnt);
+        a.cov[2 * t] = lo;
+        a.cov[2 * t + 1] = cnt;
+      } else {
+        lo = a.cov[2 * t];
+        cnt = a.cov[2 * t + 1];
+      }
+    }
+    bool ready = act;
+    for (uint32_t i = 0; i < cnt && ready; ++i) ready = a.done[lo + i] < a.round;
+    fill_ready<false>(a.out, ready, dst, src, len, a.serial);
+    if (ready) a.done[t] = uint8_t(a.round);
+    const bool left = act && !ready;
+    const uint64_t m = __ballot(left);
+    if (m) {
+      uint32_t at = 0;
+      if (lane == 0) at = atomicAdd(a.cnt_out, uint32_t(__popcll(m)));
+      at = __shfl(at, 0, 64);
+      if (left) a.list_out[at + lanes_below(m)] = t;
     }
   }
 }
 
-__global__ __launch_bounds__(64 * kCopyWaves) void k_copy(CopyArgs a) {
+// Persistent finish: 64-token chunks in output order by ticket; each wave
+// polls its unfinished tokens' covering tokens and copies a token once they
+// are all done.  Output bytes and done flags use agent-coherent accesses and
+// a store-completion wait precedes each done flag, so a flag seen by another
+// XCD implies its bytes are visible there.  A token waits only on
+// lower-indexed tokens, which lower tickets hold, so every wait ends.
+__global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
   const uint32_t lane = lane_id();
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   for (;;) {
@@ -639,55 +767,30 @@ __global__ __launch_bounds__(64 * kCopyWaves) void k_copy(CopyArgs a) {
     if (lane == 0) chunk = atomicAdd(&a.st->ticket, 1u);
     chunk = __shfl(chunk, 0, 64);
     if (chunk >= a.n_chunks) break;
-    const uint64_t ti = uint64_t(chunk) * 64 + lane;
-    bool pending = ti < a.n_tok;
+    const uint32_t t = chunk * 64 + lane;
+    bool pending = t < a.n_tok && a.done[t] == kPending;
+    if (!__ballot(pending)) continue;
     uint64_t src = 0, dst = 0;
-    uint32_t len = 0;
+    uint32_t len = 0, lo = 0, cnt = 0;
     if (pending) {
-      src = a.tok[2 * ti];
-      const uint64_t w = a.tok[2 * ti + 1];
-      dst = w & ((1ull << 48) - 1);
-      len = uint32_t(w >> 48) + 1;
+      token_at(a.tok, t, src, dst, len);
+      lo = a.cov[2 * t];
+      cnt = a.cov[2 * t + 1];
     }
-    const uint64_t dist = dst - src;
-    const uint64_t s1 = src + (dist < len ? dist : len);
     uint64_t spins = 0;
     while (__ballot(pending)) {
-      const bool ready = pending && source_ready(a.bits, a.win_lo, src, s1);
-      const uint64_t rm = __ballot(ready);
-      if (rm) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (a.serial) {
-          if (ready) copy_lane(a.out, dst, src, len);
-        } else {
-          const bool lng = ready && len >= kLongToken;
-          if (ready && !lng) copy_lane(a.out, dst, src, len);
-          uint64_t lm = __ballot(lng);
-          while (lm) {  // long tokens: the whole wave fills them, period-aware
-            const int l = __builtin_ctzll(lm);
-            lm &= lm - 1;
-            const uint64_t d = __shfl((unsigned long long)dst, l, 64);
-            const uint64_t sr = __shfl((unsigned long long)src, l, 64);
-            const uint32_t n = __shfl(len, l, 64);
-            const uint64_t dd = d - sr;
-            if (dd >= n) {
-              for (uint32_t k = lane; k < n; k += 64) a.out[d + k] = a.out[sr + k];
-            } else {
-              const uint32_t step = uint32_t(64 % dd);
-              uint32_t j = uint32_t(lane % dd);
-              for (uint32_t k = lane; k < n; k += 64) {
-                a.out[d + k] = a.out[sr + j];
-                j += step;
-                if (j >= dd) j -= uint32_t(dd);
-              }
-            }
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (ready) mark_final(a.bits, a.win_lo, dst, dst + len);
+      bool ready = pending;
+      for (uint32_t i = 0; i < cnt && ready; ++i)
+        ready = __hip_atomic_load(a.done + lo + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kPending;
+      if (__ballot(ready)) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        fill_ready<true>(a.out, ready, dst, src, len, a.serial);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the bytes are out before the flags
+        if (ready) __hip_atomic_store(a.done + t, uint8_t(a.round), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         pending = pending && !ready;
       } else {
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
         if (++spins > a.spin_limit ||
             ((spins & 63) == 0 && __hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
           if (lane == 0 && spins > a.spin_limit) report(a.st, AX_E_DEVICE, ~0ull);
@@ -702,12 +805,14 @@ __global__ void k_init(DevStatus* st) {
   if (threadIdx.x == 0) {
     st->err = 0;
     st->bad_block = ~0ull;
-    st->ticket = 0;
   }
 }
 
-__global__ void k_reset_ticket(DevStatus* st) {
-  if (threadIdx.x == 0) st->ticket = 0;
+__global__ void k_window_init(DevStatus* st) {
+  if (threadIdx.x == 0) {
+    st->ticket = 0;
+    st->count[0] = st->count[1] = st->count[2] = 0;
+  }
 }
 
 // --------------------------------------------------------------- host side --
@@ -715,7 +820,7 @@ __global__ void k_reset_ticket(DevStatus* st) {
 inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
 struct Layout {
-  uint64_t status, nsym, lit, cmd, off, len, tok, bits, total;
+  uint64_t status, nsym, lit, cmd, off, len, tok, cov, done, list0, list1, total;
 };
 
 }  // namespace
@@ -729,6 +834,7 @@ struct aceapex_decoder {
   uint64_t window_tok_max = 0; // most tokens in any window
   uint32_t off_cap = 0, len_cap = 0;
   int copy_grid = 0;
+  int bulk_rounds = 4;
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool events_ok = false;
@@ -747,8 +853,12 @@ Layout make_layout(const aceapex_decoder& d) {
   L.cmd = at, at = align256(at + W * B);
   L.off = at, at = align256(at + W * d.off_cap);
   L.len = at, at = align256(at + W * d.len_cap);
-  L.tok = at, at = align256(at + 16 * std::max<uint64_t>(1, d.window_tok_max));
-  L.bits = at, at = align256(at + W * (B / 8));
+  const uint64_t T = std::max<uint64_t>(1, d.window_tok_max);
+  L.tok = at, at = align256(at + 16 * T);
+  L.cov = at, at = align256(at + 8 * T);
+  L.done = at, at = align256(at + T);
+  L.list0 = at, at = align256(at + 4 * T);
+  L.list1 = at, at = align256(at + 4 * T);
   L.total = at;
   return L;
 }
@@ -834,7 +944,7 @@ int aceapex_decoder_create(const uint8_t* h, uint64_t h_len, const uint8_t* d_ar
   int dev = 0, cus = 0, occ = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_copy), 64 * kCopyWaves, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_tail), kCopyThreads, 0);
   d->copy_grid = std::max(1, cus) * std::max(1, occ);
   *out = d;
   return AX_OK;
@@ -872,6 +982,18 @@ int aceapex_decoder_set_timing(aceapex_decoder* d, int enable) {
   return AX_OK;
 }
 
+int aceapex_decoder_set_option(aceapex_decoder* d, int option, int64_t value) {
+  if (!d) return ax::fail(AX_E_ARG, "null decoder");
+  switch (option) {
+    case AX_OPT_BULK_ROUNDS:
+      if (value < 1 || value > 250) return ax::fail(AX_E_ARG, "bulk rounds must be in [1, 250]");
+      d->bulk_rounds = int(value);
+      return AX_OK;
+    default:
+      return ax::fail(AX_E_ARG, "unknown option");
+  }
+}
+
 int aceapex_decoder_stage_ms(aceapex_decoder* d, float* ans, float* parse, float* copy) {
   if (!d || !ans || !parse || !copy) return ax::fail(AX_E_ARG, "null argument");
   if (!d->events_ok) return ax::fail(AX_E_ARG, "timing not enabled");
@@ -902,6 +1024,7 @@ int aceapex_decode_all(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, voi
   for (uint64_t b0 = 0; b0 < nb; b0 += d->window_blocks) {
     const uint32_t items = uint32_t(std::min<uint64_t>(nb - b0, d->window_blocks));
     const bool first = b0 == 0, last = b0 + items == nb;
+    hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st);
     AnsArgs aa{d->d_arc, I.header_bytes, b0, items, uint32_t(B), w + L.lit, w + L.cmd, w + L.off, w + L.len,
                d->off_cap, d->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
     if (timed && first) (void)hipEventRecord(d->ev[0], s);
@@ -910,17 +1033,31 @@ int aceapex_decode_all(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, voi
     const uint64_t t0 = d->mpre[b0], t1 = d->mpre[b0 + items];
     ParseArgs pa{d->d_arc, I.n_bytes, b0, items, uint32_t(B), I.min_match, w + L.lit, w + L.cmd, w + L.off,
                  w + L.len, d->off_cap, d->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), t0, t1 - t0,
-                 reinterpret_cast<uint64_t*>(w + L.tok), d_out, reinterpret_cast<uint32_t*>(w + L.bits), st};
+                 reinterpret_cast<uint64_t*>(w + L.tok), w + L.done, d_out, st};
     hipLaunchKernelGGL(k_parse, dim3(items), dim3(kParseThreads), 0, s, pa);
     if (timed && first) (void)hipEventRecord(d->ev[2], s);
-    if (!first) hipLaunchKernelGGL(k_reset_ticket, dim3(1), dim3(64), 0, s, st);
-    const uint64_t ntok = t1 - t0, chunks = (ntok + 63) / 64;
-    if (chunks) {
+    const uint32_t ntok = uint32_t(t1 - t0);
+    if (ntok) {
+      uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(w + L.list0), reinterpret_cast<uint32_t*>(w + L.list1)};
       CopyArgs ca{reinterpret_cast<const uint64_t*>(w + L.tok), ntok, b0 * B, d_out,
-                  reinterpret_cast<uint32_t*>(w + L.bits), st, chunks, 1ull << 22, copy_mode == AX_COPY_SERIAL};
-      const uint64_t waves_needed = chunks, wg_needed = (waves_needed + kCopyWaves - 1) / kCopyWaves;
-      const uint32_t grid = uint32_t(std::min<uint64_t>(wg_needed, uint64_t(d->copy_grid)));
-      hipLaunchKernelGGL(k_copy, dim3(grid), dim3(64 * kCopyWaves), 0, s, ca);
+                  reinterpret_cast<uint32_t*>(w + L.cov), w + L.done, nullptr, lists[0], nullptr,
+                  &st->count[0], &st->count[1], 0, st, (ntok + 63) / 64, 1ull << 22,
+                  copy_mode == AX_COPY_SERIAL};
+      const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, 4096));
+      hipLaunchKernelGGL(k_round<true>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
+      for (int r = 1; r < d->bulk_rounds; ++r) {
+        ca.round = uint32_t(r);
+        ca.list_in = lists[(r - 1) & 1];
+        ca.list_out = lists[r & 1];
+        ca.cnt_in = &st->count[(r - 1) % 3];
+        ca.cnt_out = &st->count[r % 3];
+        ca.cnt_clear = &st->count[(r + 1) % 3];
+        hipLaunchKernelGGL(k_round<false>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
+      }
+      ca.round = uint32_t(d->bulk_rounds);
+      const uint32_t tgrid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads,
+                                                         uint64_t(d->copy_grid)));
+      hipLaunchKernelGGL(k_tail, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);
     }
     if (timed && last) (void)hipEventRecord(d->ev[3], s);
   }

@@ -76,7 +76,8 @@ struct Chains {
 // Encode block b into streams; forced (nullable) marks positions that must
 // stay literal.  cmds (nullable) receives the commands.
 void encode_block(const uint8_t* in, uint64_t n, const Params& P, const Chains& ch, const uint8_t* forced,
-                  uint64_t b, BlockStreams& bs, std::vector<Cmd>* cmds, uint64_t* n_rep, uint64_t* n_mbytes) {
+                  uint64_t b, BlockStreams& bs, std::vector<Cmd>* cmds, uint64_t* n_rep, uint64_t* n_mbytes,
+                  uint64_t* n_srcbytes) {
   const auto& p = P.p;
   const uint64_t B = p.block_size, mm = p.min_match;
   const uint64_t start = b * B, end = std::min(start + B, n);
@@ -126,6 +127,7 @@ void encode_block(const uint8_t* in, uint64_t n, const Params& P, const Chains& 
       if (cmds) cmds->push_back({pos, pos - d, uint32_t(best_rep), 2});
       ++*n_rep;
       *n_mbytes += best_rep;
+      *n_srcbytes += std::min<uint64_t>(best_rep, d);
       pos += best_rep;
       run = pos;
     } else if (best_abs >= abs_need) {
@@ -134,6 +136,7 @@ void encode_block(const uint8_t* in, uint64_t n, const Params& P, const Chains& 
       hist[3] = hist[2], hist[2] = hist[1], hist[1] = hist[0], hist[0] = pos - abs_src;
       if (cmds) cmds->push_back({pos, abs_src, uint32_t(best_abs), 1});
       *n_mbytes += best_abs;
+      *n_srcbytes += std::min<uint64_t>(best_abs, pos - abs_src);
       pos += best_abs;
       run = pos;
     } else {
@@ -147,7 +150,7 @@ struct Encoded {
   std::vector<std::vector<uint8_t>> block_bytes;  // serialised block payloads
   std::vector<uint64_t> block_matches;
   std::vector<std::vector<Cmd>> block_cmds;       // only with a depth cap
-  uint64_t n_commands = 0, n_rep = 0, n_mbytes = 0, n_lit = 0;
+  uint64_t n_commands = 0, n_rep = 0, n_mbytes = 0, n_lit = 0, n_src = 0, n_off = 0, n_len = 0;
 };
 
 unsigned thread_count(const aceapex_encode_params& p) {
@@ -168,7 +171,7 @@ int encode_pass(const uint8_t* in, uint64_t n, const Params& P, const uint8_t* f
   if (P.window) seg = std::max<uint64_t>(uint64_t(1) << 30, B);
   if (!P.window && n >= kNil) return AX_E_UNSUPPORTED;  // 32-bit chain links need a window
   seg = (seg + B - 1) / B * B;
-  std::atomic<uint64_t> tot_cmds{0}, tot_rep{0}, tot_mb{0}, tot_lit{0};
+  std::atomic<uint64_t> tot_cmds{0}, tot_rep{0}, tot_mb{0}, tot_lit{0}, tot_src{0}, tot_off{0}, tot_len{0};
   std::atomic<int> err{0};
   Chains ch;
   for (uint64_t s0 = 0; s0 < n; s0 += seg) {
@@ -180,18 +183,21 @@ int encode_pass(const uint8_t* in, uint64_t n, const Params& P, const uint8_t* f
     std::atomic<uint64_t> next{b0};
     auto worker = [&]() {
       BlockStreams bs;
-      uint64_t cmds = 0, reps = 0, mb = 0, lit = 0;
+      uint64_t cmds = 0, reps = 0, mb = 0, lit = 0, srcb = 0, offb = 0, lenb = 0;
       std::vector<uint8_t> rec;
       for (;;) {
         uint64_t b = next.fetch_add(1);
         if (b >= b1) break;
-        encode_block(in, n, P, ch, forced, b, bs, keep_cmds ? &E.block_cmds[b] : nullptr, &reps, &mb);
+        encode_block(in, n, P, ch, forced, b, bs, keep_cmds ? &E.block_cmds[b] : nullptr, &reps, &mb, &srcb);
         cmds += bs.cmd.size();
         lit += bs.lit.size();
+        offb += bs.off.size();
+        lenb += bs.len.size();
         E.block_matches[b] = bs.n_matches;
         if (!ax::serialize_block(bs, p.rans_min_syms_per_lane, E.block_bytes[b])) err = AX_E_NOMEM;
       }
       tot_cmds += cmds, tot_rep += reps, tot_mb += mb, tot_lit += lit;
+      tot_src += srcb, tot_off += offb, tot_len += lenb;
     };
     std::vector<std::thread> pool;
     for (unsigned t = 1; t < T; ++t) pool.emplace_back(worker);
@@ -200,6 +206,7 @@ int encode_pass(const uint8_t* in, uint64_t n, const Params& P, const uint8_t* f
     if (err) return err;
   }
   E.n_commands = tot_cmds, E.n_rep = tot_rep, E.n_mbytes = tot_mb, E.n_lit = tot_lit;
+  E.n_src = tot_src, E.n_off = tot_off, E.n_len = tot_len;
   return AX_OK;
 }
 
@@ -338,6 +345,9 @@ int aceapex_encode(const uint8_t* src, uint64_t n, const aceapex_encode_params* 
       stats->n_rep = E.n_rep;
       stats->n_match_bytes = E.n_mbytes;
       stats->n_lit_bytes = E.n_lit;
+      stats->n_src_bytes = E.n_src;
+      stats->n_off_bytes = E.n_off;
+      stats->n_len_bytes = E.n_len;
       stats->max_depth = deepest;
       stats->passes = passes;
     }
