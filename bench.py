@@ -42,6 +42,7 @@ def parse_args():
     ap.add_argument("--no-rep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--threads", type=int, default=0, help="encoder threads (0 = all)")
+    ap.add_argument("--bulk-rounds", type=int, default=0, help="level-synchronous copy rounds (0 = library default)")
     return ap.parse_args()
 
 
@@ -91,6 +92,8 @@ def main():
     out = torch.empty(n, dtype=torch.uint8, device=dev)
     work = dec.workspace()
     mode = ax.COPY_SERIAL if args.copy == "serial" else ax.COPY_PERIODIC
+    if args.bulk_rounds:
+        dec.set_bulk_rounds(args.bulk_rounds)
     stream = torch.cuda.current_stream()
 
     # correctness first (poisoned output), outside the timed region
@@ -158,7 +161,7 @@ def main():
         "config": {"workload": desc, "n_bytes": n, "archive_bytes": c_bytes,
                    "ratio": round(n / c_bytes, 4), "blocks": int(dec.info.n_blocks),
                    "commands": int(st.n_commands), "matches": int(st.n_matches), "repeats": int(st.n_rep),
-                   "copy_mode": args.copy, "no_rep": bool(args.no_rep)},
+                   "copy_mode": args.copy, "no_rep": bool(args.no_rep), "bulk_rounds": args.bulk_rounds or 4},
         "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 5),
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         "stage_share": {k: round(v / max(1e-9, sum(stages.values())), 4) for k, v in stages.items()},

@@ -38,6 +38,8 @@ namespace {
 
 constexpr uint32_t kMaxB = 16384;           // largest block the device path decodes
 constexpr uint32_t kParseThreads = 256;
+constexpr uint32_t kOffStage = 4096;        // offset-stream bytes staged in LDS by k_parse
+constexpr uint32_t kLenStage = 1024;        // length-stream bytes staged in LDS by k_parse
 constexpr uint32_t kCopyThreads = 256;      // match-layer workgroup
 constexpr uint32_t kLongToken = 64;         // tokens at least this long are copied by the whole wave
 constexpr uint8_t kPending = 0xFF;          // done[] value of a token not yet copied
@@ -294,6 +296,9 @@ __device__ inline Map4 map_after(const Map4& g, const Map4& f) {
   for (int i = 0; i < 4; ++i) h.s[i] = map_pick(f, g.s[i]);
   return h;
 }
+__device__ inline uint64_t pick4(const uint64_t h[4], uint64_t j) {
+  return j == 0 ? h[0] : j == 1 ? h[1] : j == 2 ? h[2] : h[3];
+}
 __device__ inline Map4 map_identity() { return Map4{{kTagRef | 0, kTagRef | 1, kTagRef | 2, kTagRef | 3}}; }
 __device__ inline Map4 map_shfl_up(const Map4& m, int o) {
   Map4 r;
@@ -313,6 +318,8 @@ struct ParseShared {
   uint32_t runbits[kMaxB / 32];   // run starts in the chunk's literal space
   uint16_t runpre[kMaxB / 32];    // run starts in earlier words
   uint16_t rundelta[kParseThreads];
+  uint8_t offb[kOffStage];        // the block's decoded offset stream, when it fits
+  uint8_t lenb[kLenStage];        // the block's decoded length stream, when it fits
   uint64_t offval[kParseThreads];
   uint32_t lenval[kParseThreads];
   uint64_t wsum[4][2];
@@ -451,8 +458,17 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
   const uint64_t tok_lo = mpre[b] - a.tok_first, tok_n = mpre[b + 1] - mpre[b];
 
   if (t == 0) sh.bad = (n_lit > B || n_cmd > B || n_len > a.len_cap || n_off > a.off_cap) ? 1 : 0;
+  // stage the offset and length streams in LDS (16-byte loads; slots are 16-aligned)
+  if (n_off <= kOffStage)
+    for (uint32_t k = 16 * t; k < n_off; k += 16 * kParseThreads)
+      *reinterpret_cast<uint4*>(sh.offb + k) = *reinterpret_cast<const uint4*>(offs + k);
+  if (n_len <= kLenStage)
+    for (uint32_t k = 16 * t; k < n_len; k += 16 * kParseThreads)
+      *reinterpret_cast<uint4*>(sh.lenb + k) = *reinterpret_cast<const uint4*>(lens + k);
   __syncthreads();
   bool failed = sh.bad != 0;
+  const uint8_t* offv = n_off <= kOffStage ? sh.offb : offs;
+  const uint8_t* lenv = n_len <= kLenStage ? sh.lenb : lens;
 
   uint32_t dst = 0, litp = 0, offc = 0, lenc = 0;
   uint64_t ntok = 0;
@@ -475,13 +491,13 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     const uint32_t n_tokc = uint32_t(ctot >> 48);
     // length and offset values of this chunk
     uint64_t* lv64 = sh.offval;  // reuse: lengths first, then offsets
-    if (!leb_values(lens, n_len, &lenc, n_esc, lv64, sh)) { failed = true; break; }
+    if (!leb_values(lenv, n_len, &lenc, n_esc, lv64, sh)) { failed = true; break; }
     if (t < n_esc) {
       const uint64_t e = lv64[t];
       sh.lenval[t] = e > B ? 0xFFFFFFFFu : uint32_t(e);
     }
     __syncthreads();
-    if (!leb_values(offs, n_off, &offc, n_k1, sh.offval, sh)) { failed = true; break; }
+    if (!leb_values(offv, n_off, &offc, n_k1, sh.offval, sh)) { failed = true; break; }
     uint32_t len = 0;
     if (valid) {
       const uint32_t ext = esc ? sh.lenval[esc_i] : 0u;
@@ -505,14 +521,16 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     } else if (is2) {
       const uint32_t r = (c >> 2) & 3;
       mine.s[0] = kTagRef | r;
-      for (uint32_t k = 1; k <= 3; ++k) mine.s[k] = kTagRef | (k <= r ? k - 1 : k);
+      mine.s[1] = kTagRef | (r >= 1 ? 0u : 1u);
+      mine.s[2] = kTagRef | (r >= 2 ? 1u : 2u);
+      mine.s[3] = kTagRef | (r >= 3 ? 2u : 3u);
     }
     Map4 mtot;
     const Map4 before = block_excl_map(mine, &mtot, sh);
     if (is2) {
       const uint32_t r = (c >> 2) & 3;
-      const uint64_t g = before.s[r];
-      const uint64_t d = (g & kTagRef) ? hist[g & 3] : g;
+      const uint64_t g = pick4(before.s, r);
+      const uint64_t d = (g & kTagRef) ? pick4(hist, g & 3) : g;
       if (d > absdst) bad = true;
       else src = absdst - d;
     }
@@ -549,17 +567,26 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
       if (2 * t + 1 < nwords) sh.runpre[2 * t + 1] = uint16_t(pre + c2[0]);
     }
     __syncthreads();
-    for (uint32_t j = t; j < chunk_lit; j += kParseThreads) {  // place the chunk's literal bytes
-      const uint32_t w = j >> 5;
-      const uint32_t r = sh.runpre[w] + __popc(sh.runbits[w] & (0xFFFFFFFFu >> (31 - (j & 31)))) - 1;
-      sh.tile[litp + j + sh.rundelta[r]] = lit[litp + j];
+    // place the chunk's literal bytes: aligned 16-byte groups of the literal
+    // stream, each byte moved by its run's (output - literal index) delta
+    for (uint32_t g = (litp >> 4) + t; g < ((litp + chunk_lit + 15) >> 4); g += kParseThreads) {
+      const uint4 q = *reinterpret_cast<const uint4*>(lit + 16 * g);
+      const uint32_t word[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (uint32_t k = 0; k < 16; ++k) {
+        const uint32_t li = 16 * g + k;
+        if (li < litp || li >= litp + chunk_lit) continue;
+        const uint32_t j = li - litp, w = j >> 5;
+        const uint32_t r = sh.runpre[w] + __popc(sh.runbits[w] & (0xFFFFFFFFu >> (31 - (j & 31)))) - 1;
+        sh.tile[li + sh.rundelta[r]] = uint8_t(word[k >> 2] >> (8 * (k & 3)));
+      }
     }
     __syncthreads();
     dst += uint32_t(ptot & 0xFFFFFFFFu);
     litp += chunk_lit;
     ntok += n_tokc;
     uint64_t nh[4];
-    for (int k = 0; k < 4; ++k) nh[k] = (mtot.s[k] & kTagRef) ? hist[mtot.s[k] & 3] : mtot.s[k];
+    for (int k = 0; k < 4; ++k) nh[k] = (mtot.s[k] & kTagRef) ? pick4(hist, mtot.s[k] & 3) : mtot.s[k];
     for (int k = 0; k < 4; ++k) hist[k] = nh[k];
   }
   if (!failed && (dst != blen || litp != n_lit || lenc != n_len || offc != n_off || ntok != tok_n)) failed = true;
@@ -579,6 +606,9 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
 
 struct CopyArgs {
   const uint64_t* tok;       // window tokens in output order
+  const uint64_t* mpre;      // archive index: cumulative match count per block
+  uint64_t tok_first;        // cumulative match count at the window start
+  uint32_t B;
   uint32_t n_tok;
   uint64_t win_lo;           // bytes below are final
   uint8_t* out;
@@ -603,19 +633,20 @@ __device__ inline void token_at(const uint64_t* tok, uint64_t t, uint64_t& src, 
   len = uint32_t(w >> 48) + 1;
 }
 
-// Tokens [lo, lo+cnt) are those whose destinations meet [s0, s1); tokens are
-// disjoint and sorted by destination.
-__device__ inline void find_cover(const uint64_t* tok, uint32_t n, uint64_t s0, uint64_t s1, uint32_t& lo,
-                                  uint32_t& cnt) {
-  uint32_t a = 0, b = n;
-  while (a < b) {  // first token ending after s0
-    const uint32_t mid = (a + b) >> 1;
-    const uint64_t w = tok[2 * uint64_t(mid) + 1];
-    if ((w & ((1ull << 48) - 1)) + (w >> 48) + 1 <= s0) a = mid + 1; else b = mid;
+// Tokens [lo, lo+cnt) are those whose destinations meet [s0, s1).  Tokens
+// are disjoint and sorted by destination, and the archive index gives the
+// token range of every block, so the search runs inside the block holding s0.
+__device__ inline void find_cover(const CopyArgs& a, uint64_t s0, uint64_t s1, uint32_t& lo, uint32_t& cnt) {
+  const uint64_t sb = s0 / a.B;
+  uint32_t x = uint32_t(a.mpre[sb] - a.tok_first), y = uint32_t(a.mpre[sb + 1] - a.tok_first);
+  while (x < y) {  // first token ending after s0 (or the next block's first token)
+    const uint32_t mid = (x + y) >> 1;
+    const uint64_t w = a.tok[2 * uint64_t(mid) + 1];
+    if ((w & ((1ull << 48) - 1)) + (w >> 48) + 1 <= s0) x = mid + 1; else y = mid;
   }
-  lo = a;
+  lo = x;
   cnt = 0;
-  while (a + cnt < n && (tok[2 * uint64_t(a + cnt) + 1] & ((1ull << 48) - 1)) < s1) ++cnt;
+  while (x + cnt < a.n_tok && (a.tok[2 * uint64_t(x + cnt) + 1] & ((1ull << 48) - 1)) < s1) ++cnt;
 }
 
 template <bool COH>
@@ -730,7 +761,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
       if (FIRST) {
         const uint64_t dist = dst - src;
         const uint64_t s1 = src + (dist < len ? dist : len);
-        if (s1 > a.win_lo) find_cover(a.tok, a.n_tok, src < a.win_lo ? a.win_lo : src, s1, lo, cnt);
+        if (s1 > a.win_lo) find_cover(a, src < a.win_lo ? a.win_lo : src, s1, lo, cnt);
         a.cov[2 * t] = lo;
         a.cov[2 * t + 1] = cnt;
       } else {
@@ -1039,7 +1070,8 @@ int aceapex_decode_all(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, voi
     const uint32_t ntok = uint32_t(t1 - t0);
     if (ntok) {
       uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(w + L.list0), reinterpret_cast<uint32_t*>(w + L.list1)};
-      CopyArgs ca{reinterpret_cast<const uint64_t*>(w + L.tok), ntok, b0 * B, d_out,
+      const uint64_t* mpre_dev = reinterpret_cast<const uint64_t*>(d->d_arc + 64) + (nb + 1);
+      CopyArgs ca{reinterpret_cast<const uint64_t*>(w + L.tok), mpre_dev, t0, uint32_t(B), ntok, b0 * B, d_out,
                   reinterpret_cast<uint32_t*>(w + L.cov), w + L.done, nullptr, lists[0], nullptr,
                   &st->count[0], &st->count[1], 0, st, (ntok + 63) / 64, 1ull << 22,
                   copy_mode == AX_COPY_SERIAL};
@@ -1052,7 +1084,8 @@ int aceapex_decode_all(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, voi
         ca.cnt_in = &st->count[(r - 1) % 3];
         ca.cnt_out = &st->count[r % 3];
         ca.cnt_clear = &st->count[(r + 1) % 3];
-        hipLaunchKernelGGL(k_round<false>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
+        // later rounds see the previous round's leftovers only: a smaller grid
+        hipLaunchKernelGGL(k_round<false>, dim3(std::min<uint32_t>(grid, 512)), dim3(kCopyThreads), 0, s, ca);
       }
       ca.round = uint32_t(d->bulk_rounds);
       const uint32_t tgrid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads,
