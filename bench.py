@@ -43,6 +43,8 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--threads", type=int, default=0, help="encoder threads (0 = all)")
     ap.add_argument("--bulk-rounds", type=int, default=0, help="level-synchronous copy rounds (0 = library default)")
+    ap.add_argument("--tail-chunks", type=int, default=0, help="chunks per persistent-launch ticket (0 = default)")
+    ap.add_argument("--fill", default="", help="fill modes 'R,T' for rounds and tail (0 lane/wave, 1 segmented)")
     return ap.parse_args()
 
 
@@ -94,6 +96,12 @@ def main():
     mode = ax.COPY_SERIAL if args.copy == "serial" else ax.COPY_PERIODIC
     if args.bulk_rounds:
         dec.set_bulk_rounds(args.bulk_rounds)
+    if args.tail_chunks:
+        dec.set_option(ax.OPT_TAIL_CHUNKS, args.tail_chunks)
+    if args.fill:
+        fr, ft = (int(v) for v in args.fill.split(","))
+        dec.set_option(ax.OPT_FILL_ROUNDS, fr)
+        dec.set_option(ax.OPT_FILL_TAIL, ft)
     stream = torch.cuda.current_stream()
 
     # correctness first (poisoned output), outside the timed region
@@ -161,7 +169,7 @@ def main():
         "config": {"workload": desc, "n_bytes": n, "archive_bytes": c_bytes,
                    "ratio": round(n / c_bytes, 4), "blocks": int(dec.info.n_blocks),
                    "commands": int(st.n_commands), "matches": int(st.n_matches), "repeats": int(st.n_rep),
-                   "copy_mode": args.copy, "no_rep": bool(args.no_rep), "bulk_rounds": args.bulk_rounds or 4},
+                   "copy_mode": args.copy, "no_rep": bool(args.no_rep), "bulk_rounds": args.bulk_rounds or 4, "fill": args.fill or "1,0", "tail_chunks": args.tail_chunks or 1},
         "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 5),
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         "stage_share": {k: round(v / max(1e-9, sum(stages.values())), 4) for k, v in stages.items()},

@@ -155,6 +155,16 @@ int aceapex_decoder_set_timing(aceapex_decoder* dec, int enable);
  *     launch each, plain cached accesses) before the persistent launch that
  *     finishes the deeper tokens, in [1, 250] (default 4). */
 enum { AX_OPT_BULK_ROUNDS = 1 };
+/*   AX_OPT_FILL_ROUNDS / AX_OPT_FILL_TAIL  how a wave fills its ready tokens
+ *     in the first round / in the later rounds and the persistent launch:
+ *     0 short tokens one lane each and long ones by the whole wave, 1 all
+ *     ready tokens laid end to end and split evenly over the lanes
+ *     (defaults 1 / 0). */
+enum { AX_OPT_FILL_ROUNDS = 2, AX_OPT_FILL_TAIL = 3 };
+/*   AX_OPT_TAIL_CHUNKS  consecutive 64-token chunks a wave of the persistent
+ *     launch takes per ticket, in [1, 64] (default 1): fewer tickets (one
+ *     global counter) against less overlap of dependent chunks. */
+enum { AX_OPT_TAIL_CHUNKS = 4 };
 int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
 
 /* Read the device status word of a workspace after the work queued on

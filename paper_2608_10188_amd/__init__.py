@@ -24,7 +24,7 @@ EXPORTS = [
     "aceapex_decoder_info", "aceapex_decoder_workspace", "aceapex_decode_all", "aceapex_decoder_stage_ms",
     "aceapex_decoder_set_timing", "aceapex_decoder_status", "aceapex_decoder_set_option",
 ]
-OPT_BULK_ROUNDS = 1
+OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS = 1, 2, 3, 4
 
 
 class AceapexError(RuntimeError):

@@ -41,8 +41,10 @@ constexpr uint32_t kParseThreads = 256;
 constexpr uint32_t kOffStage = 4096;        // offset-stream bytes staged in LDS by k_parse
 constexpr uint32_t kLenStage = 1024;        // length-stream bytes staged in LDS by k_parse
 constexpr uint32_t kCopyThreads = 256;      // match-layer workgroup
-constexpr uint32_t kLongToken = 64;         // tokens at least this long are copied by the whole wave
 constexpr uint8_t kPending = 0xFF;          // done[] value of a token not yet copied
+constexpr uint32_t kSub = 64;               // pending-list sublists (one counter each, 256 B apart)
+constexpr uint32_t kCounterStride = 64;     // u32 between two sublist counters
+constexpr uint32_t kMaxRoundGrid = 4096;    // workgroups of a round launch
 constexpr uint64_t kTagRef = 1ull << 63;    // history-map slot holding an input index
 
 struct DevStatus {
@@ -50,8 +52,8 @@ struct DevStatus {
   uint32_t pad0;
   unsigned long long bad_block;
   uint32_t ticket;
-  uint32_t count[3];  // pending-list lengths of the level-synchronous rounds
-  uint32_t pad1[56];
+  uint32_t long_count;
+  uint32_t pad1[58];
 };
 static_assert(sizeof(DevStatus) == 256, "status block is 256 bytes");
 
@@ -614,16 +616,21 @@ struct CopyArgs {
   uint8_t* out;
   uint32_t* cov;             // per token: first covering token, count
   uint8_t* done;             // per token: round that copied it, or kPending
-  const uint32_t* list_in;   // pending tokens of the previous round
+  const uint32_t* list_in;   // pending tokens of the previous round: kSub sublists of sub_cap
   uint32_t* list_out;
-  const uint32_t* cnt_in;
+  const uint32_t* cnt_in;    // kSub counters, kCounterStride apart
   uint32_t* cnt_out;
-  uint32_t* cnt_clear;       // the counter the next round writes
+  uint32_t* cnt_clear;       // the counters the next round writes
+  uint32_t sub_cap;
+  uint32_t* long_list;       // round 0: ready tokens of at least kSplitToken bytes
+  uint32_t* long_cnt;
   uint32_t round;
   DevStatus* st;
   uint32_t n_chunks;
   uint64_t spin_limit;
   int serial;
+  int fill_round, fill_tail;  // kFillLaneWave or kFillSegmented
+  uint32_t tail_chunks;       // consecutive 64-token chunks per persistent-launch ticket
 };
 
 __device__ inline void token_at(const uint64_t* tok, uint64_t t, uint64_t& src, uint64_t& dst, uint32_t& len) {
@@ -660,6 +667,16 @@ __device__ inline void stb(uint8_t* p, uint8_t v) {
   else *p = v;
 }
 
+// The serial ablation: one lane, byte after byte, reading the bytes it may
+// itself have just written (a self-overlapping match is a dependency chain).
+template <bool COH>
+__device__ inline void fill_serial(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len) {
+  for (uint32_t k = 0; k < len; ++k) {
+    stb<COH>(out + dst + k, ldb<COH>(out + src + k));
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // the next load may read this byte
+  }
+}
+
 // One lane fills a token as a periodic fill: sixteen source loads in flight,
 // then sixteen stores.  The source index runs over the period dist (for
 // dist >= len it never wraps and the fill is a plain copy).
@@ -683,59 +700,114 @@ __device__ inline void fill_lane(uint8_t* out, uint64_t dst, uint64_t src, uint3
   }
 }
 
-// The serial ablation: one lane, byte after byte, reading the bytes it may
-// itself have just written (a self-overlapping match is a dependency chain).
-template <bool COH>
-__device__ inline void fill_serial(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len) {
-  for (uint32_t k = 0; k < len; ++k) {
-    stb<COH>(out + dst + k, ldb<COH>(out + src + k));
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // the next load may read this byte
-  }
-}
-
-// The whole wave fills one long token: four bytes per lane in flight.
+// The whole wave fills one long token: eight bytes per lane in flight.
 template <bool COH>
 __device__ inline void fill_wave(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len, uint32_t lane) {
   const uint64_t dist = dst - src;
   const uint64_t step = 64 % dist;
   uint64_t j = lane % dist;
-  for (uint32_t k0 = lane; k0 < len; k0 += 256) {
-    uint64_t idx[4];
+  for (uint32_t k0 = lane; k0 < len; k0 += 512) {
+    uint64_t idx[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       idx[q] = j;
       j += step;
       if (j >= dist) j -= dist;
     }
-    uint8_t v[4];
+    uint8_t v[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (k0 + 64 * q < len) ? ldb<COH>(out + src + idx[q]) : uint8_t(0);
+    for (int q = 0; q < 8; ++q) v[q] = (k0 + 64 * q < len) ? ldb<COH>(out + src + idx[q]) : uint8_t(0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 8; ++q)
       if (k0 + 64 * q < len) stb<COH>(out + dst + k0 + 64 * q, v[q]);
   }
 }
 
-// Copy this wave's ready tokens: short ones lane by lane, long ones by the
-// whole wave.
+constexpr uint32_t kLongToken = 64;     // lane/wave fill: tokens at least this long use the whole wave
+constexpr uint32_t kSplitToken = 1024;  // round 0: tokens at least this long get a workgroup each
+
+// Per-wave staging of the ready tokens for the segmented fill.
+struct FillStage {
+  uint32_t end[64];   // inclusive prefix of lengths (0 for tokens not copied)
+  uint32_t len[64];
+  uint64_t dst[64];
+  uint64_t src[64];
+};
+
+constexpr uint32_t kFillBytes = 8;  // consecutive bytes per lane per pass
+enum { kFillLaneWave = 0, kFillSegmented = 1 };
+
+// Segmented periodic fill of this wave's ready tokens: their bytes are laid
+// end to end and every lane takes kFillBytes consecutive ones per pass, so a
+// pass issues 64 * kFillBytes independent source loads before its stores,
+// whatever the mix of short and long tokens.  Byte k of a token comes from
+// src + (k mod dist) (dist >= len: a plain copy).
 template <bool COH>
-__device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64_t src, uint32_t len, int serial) {
+__device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64_t src, uint32_t len, int serial,
+                                  int fill_mode, FillStage& fs) {
   const uint32_t lane = lane_id();
   if (serial) {
     if (ready) fill_serial<COH>(out, dst, src, len);
     return;
   }
-  const bool lng = ready && len >= kLongToken;
-  if (ready && !lng) fill_lane<COH>(out, dst, src, len);
-  uint64_t lm = __ballot(lng);
-  while (lm) {
-    const int l = __builtin_ctzll(lm);
-    lm &= lm - 1;
-    const uint64_t d = __shfl((unsigned long long)dst, l, 64);
-    const uint64_t sr = __shfl((unsigned long long)src, l, 64);
-    const uint32_t n = __shfl(len, l, 64);
-    fill_wave<COH>(out, d, sr, n, lane);
+  if (fill_mode == kFillLaneWave) {  // short tokens lane by lane, long ones by the whole wave
+    const bool lng = ready && len >= kLongToken;
+    if (ready && !lng) fill_lane<COH>(out, dst, src, len);
+    uint64_t lm = __ballot(lng);
+    while (lm) {
+      const int l = __builtin_ctzll(lm);
+      lm &= lm - 1;
+      fill_wave<COH>(out, __shfl((unsigned long long)dst, l, 64), __shfl((unsigned long long)src, l, 64),
+                     __shfl(len, l, 64), lane);
+    }
+    return;
   }
+  const uint32_t mine = ready ? len : 0u;
+  uint32_t total;
+  const uint32_t excl = wave_excl_sum(mine, &total);
+  fs.end[lane] = excl + mine;
+  fs.len[lane] = mine;
+  fs.dst[lane] = dst;
+  fs.src[lane] = src;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  for (uint32_t base = 0; base < total; base += 64 * kFillBytes) {
+    const uint32_t f0 = base + lane * kFillBytes;
+    uint64_t at[kFillBytes];
+    uint64_t to[kFillBytes];
+    uint8_t v[kFillBytes];
+    if (f0 < total) {
+      uint32_t l = 0;  // first token whose end exceeds f0
+#pragma unroll
+      for (uint32_t step = 32; step; step >>= 1)
+        if (fs.end[l + step - 1] <= f0) l += step;
+      uint32_t e = fs.end[l], start = e - fs.len[l];
+      uint64_t d = fs.dst[l], sr = fs.src[l], dist = d - sr;
+      uint64_t k = f0 - start;  // < 2^16: a token lies inside one block
+      uint64_t j = dist > k ? k : uint64_t(uint32_t(k) % uint32_t(dist));
+#pragma unroll
+      for (uint32_t q = 0; q < kFillBytes; ++q) {
+        const uint32_t f = f0 + q;
+        if (f < total && f >= e) {  // next token with bytes
+          do { ++l; } while (fs.len[l] == 0);
+          e = fs.end[l];
+          start = e - fs.len[l];
+          d = fs.dst[l], sr = fs.src[l], dist = d - sr;
+          k = 0, j = 0;
+        }
+        at[q] = sr + j;
+        to[q] = f < total ? d + k : ~0ull;
+        ++k;
+        if (++j == dist) j = 0;
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < kFillBytes; ++q) v[q] = to[q] != ~0ull ? ldb<COH>(out + at[q]) : uint8_t(0);
+#pragma unroll
+      for (uint32_t q = 0; q < kFillBytes; ++q)
+        if (to[q] != ~0ull) stb<COH>(out + to[q], v[q]);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
 }
 
 // Level-synchronous round r.  Round 0 visits every token, records its
@@ -746,14 +818,39 @@ __device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64
 // earlier launch, so no access within a round races.
 template <bool FIRST>
 __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
+  __shared__ FillStage stage[kCopyThreads / 64];
+  __shared__ uint32_t sub_end[kSub];  // inclusive prefix of the input sublist lengths
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const uint32_t lane = lane_id();
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_clear = 0;
-  const uint32_t n_items = FIRST ? a.n_tok : *a.cnt_in;
+  FillStage& fs = stage[threadIdx.x >> 6];
+  if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
+  uint32_t n_items = a.n_tok;
+  if (!FIRST) {
+    if (threadIdx.x < 64) {
+      uint32_t tot;
+      const uint32_t c = a.cnt_in[threadIdx.x * kCounterStride];
+      sub_end[threadIdx.x] = wave_excl_sum(c, &tot) + c;
+    }
+    __syncthreads();
+    n_items = sub_end[kSub - 1];
+  }
+  const uint32_t my_sub = blockIdx.x % kSub;
   for (uint64_t base = uint64_t(blockIdx.x) * kCopyThreads; base < n_items; base += uint64_t(gridDim.x) * kCopyThreads) {
     const uint64_t item = base + threadIdx.x;
     const bool act = item < n_items;
-    const uint32_t t = act ? (FIRST ? uint32_t(item) : a.list_in[item]) : 0u;
+    uint32_t t = 0;
+    if (act) {
+      if (FIRST) {
+        t = uint32_t(item);
+      } else {  // sublist holding item
+        uint32_t sl = 0;
+#pragma unroll
+        for (uint32_t step = 32; step; step >>= 1)
+          if (sub_end[sl + step - 1] <= item) sl += step;
+        const uint32_t start = sub_end[sl] - (sl ? sub_end[sl] - sub_end[sl - 1] : sub_end[0]);
+        t = a.list_in[uint64_t(sl) * a.sub_cap + (item - start)];
+      }
+    }
     uint64_t src = 0, dst = 0;
     uint32_t len = 0, lo = 0, cnt = 0;
     if (act) {
@@ -771,16 +868,60 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     }
     bool ready = act;
     for (uint32_t i = 0; i < cnt && ready; ++i) ready = a.done[lo + i] < a.round;
-    fill_ready<false>(a.out, ready, dst, src, len, a.serial);
-    if (ready) a.done[t] = uint8_t(a.round);
+    // round 0: long ready tokens are handed to k_long (a workgroup each) so
+    // that no wave carries a block-sized fill alone
+    const bool split = FIRST && ready && !a.serial && len >= kSplitToken;
+    const uint64_t sm = __ballot(split);
+    if (sm) {
+      uint32_t at = 0;
+      if (lane == 0) at = atomicAdd(a.long_cnt, uint32_t(__popcll(sm)));
+      at = __shfl(at, 0, 64);
+      if (split) a.long_list[at + lanes_below(sm)] = t;
+    }
+    fill_ready<false>(a.out, ready && !split, dst, src, len, a.serial, FIRST ? a.fill_round : a.fill_tail, fs);
+    if (ready && !split) a.done[t] = uint8_t(a.round);
     const bool left = act && !ready;
     const uint64_t m = __ballot(left);
-    if (m) {
+    if (m) {  // leftovers go to this workgroup's sublist (counters spread over kSub addresses)
       uint32_t at = 0;
-      if (lane == 0) at = atomicAdd(a.cnt_out, uint32_t(__popcll(m)));
+      if (lane == 0) at = atomicAdd(a.cnt_out + my_sub * kCounterStride, uint32_t(__popcll(m)));
       at = __shfl(at, 0, 64);
-      if (left) a.list_out[at + lanes_below(m)] = t;
+      if (left) a.list_out[uint64_t(my_sub) * a.sub_cap + at + lanes_below(m)] = t;
     }
+  }
+}
+
+// Round 0's long tokens: one workgroup per token, sixteen bytes per thread
+// in flight; the token is marked done (round 0) once the whole group is
+// through.
+__global__ __launch_bounds__(kCopyThreads) void k_long(CopyArgs a) {
+  if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  const uint32_t n = *a.long_cnt;
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const uint32_t t = a.long_list[i];
+    uint64_t src, dst;
+    uint32_t len;
+    token_at(a.tok, t, src, dst, len);
+    const uint64_t dist = dst - src;
+    const uint64_t step = uint64_t(kCopyThreads) % dist;
+    uint64_t j = threadIdx.x % dist;
+    for (uint32_t k0 = threadIdx.x; k0 < len; k0 += 16 * kCopyThreads) {
+      uint64_t idx[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        idx[q] = j;
+        j += step;
+        if (j >= dist) j -= dist;
+      }
+      uint8_t v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = (k0 + kCopyThreads * q < len) ? a.out[src + idx[q]] : uint8_t(0);
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (k0 + kCopyThreads * q < len) a.out[dst + k0 + kCopyThreads * q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.done[t] = 0;
   }
 }
 
@@ -791,41 +932,47 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
 // XCD implies its bytes are visible there.  A token waits only on
 // lower-indexed tokens, which lower tickets hold, so every wait ends.
 __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
+  __shared__ FillStage stage[kCopyThreads / 64];
   const uint32_t lane = lane_id();
+  FillStage& fs = stage[threadIdx.x >> 6];
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  const uint32_t per = a.tail_chunks;  // consecutive chunks per ticket
+  const uint32_t n_tickets = (a.n_chunks + per - 1) / per;
   for (;;) {
-    uint32_t chunk = 0;
-    if (lane == 0) chunk = atomicAdd(&a.st->ticket, 1u);
-    chunk = __shfl(chunk, 0, 64);
-    if (chunk >= a.n_chunks) break;
-    const uint32_t t = chunk * 64 + lane;
-    bool pending = t < a.n_tok && a.done[t] == kPending;
-    if (!__ballot(pending)) continue;
-    uint64_t src = 0, dst = 0;
-    uint32_t len = 0, lo = 0, cnt = 0;
-    if (pending) {
-      token_at(a.tok, t, src, dst, len);
-      lo = a.cov[2 * t];
-      cnt = a.cov[2 * t + 1];
-    }
-    uint64_t spins = 0;
-    while (__ballot(pending)) {
-      bool ready = pending;
-      for (uint32_t i = 0; i < cnt && ready; ++i)
-        ready = __hip_atomic_load(a.done + lo + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kPending;
-      if (__ballot(ready)) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        fill_ready<true>(a.out, ready, dst, src, len, a.serial);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the bytes are out before the flags
-        if (ready) __hip_atomic_store(a.done + t, uint8_t(a.round), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        pending = pending && !ready;
-      } else {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > a.spin_limit ||
-            ((spins & 63) == 0 && __hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
-          if (lane == 0 && spins > a.spin_limit) report(a.st, AX_E_DEVICE, ~0ull);
-          return;
+    uint32_t tk = 0;
+    if (lane == 0) tk = atomicAdd(&a.st->ticket, 1u);
+    tk = __shfl(tk, 0, 64);
+    if (tk >= n_tickets) return;
+    for (uint32_t chunk = tk * per; chunk < min(tk * per + per, a.n_chunks); ++chunk) {
+      const uint32_t t = chunk * 64 + lane;
+      bool pending = t < a.n_tok && a.done[t] == kPending;
+      if (!__ballot(pending)) continue;
+      uint64_t src = 0, dst = 0;
+      uint32_t len = 0, lo = 0, cnt = 0;
+      if (pending) {
+        token_at(a.tok, t, src, dst, len);
+        lo = a.cov[2 * t];
+        cnt = a.cov[2 * t + 1];
+      }
+      uint64_t spins = 0;
+      while (__ballot(pending)) {
+        bool ready = pending;
+        for (uint32_t i = 0; i < cnt && ready; ++i)
+          ready = __hip_atomic_load(a.done + lo + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kPending;
+        if (__ballot(ready)) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          fill_ready<true>(a.out, ready, dst, src, len, a.serial, a.fill_tail, fs);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the bytes are out before the flags
+          if (ready) __hip_atomic_store(a.done + t, uint8_t(a.round), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          pending = pending && !ready;
+        } else {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > a.spin_limit ||
+              ((spins & 63) == 0 && __hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+            if (lane == 0 && spins > a.spin_limit) report(a.st, AX_E_DEVICE, ~0ull);
+            return;
+          }
         }
       }
     }
@@ -842,8 +989,12 @@ __global__ void k_init(DevStatus* st) {
 __global__ void k_window_init(DevStatus* st) {
   if (threadIdx.x == 0) {
     st->ticket = 0;
-    st->count[0] = st->count[1] = st->count[2] = 0;
+    st->long_count = 0;
   }
+}
+
+__global__ void k_clear_u32(uint32_t* p, uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
 // --------------------------------------------------------------- host side --
@@ -851,7 +1002,8 @@ __global__ void k_window_init(DevStatus* st) {
 inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
 struct Layout {
-  uint64_t status, nsym, lit, cmd, off, len, tok, cov, done, list0, list1, total;
+  uint64_t status, nsym, lit, cmd, off, len, tok, cov, done, counts, list0, list1, llist, total;
+  uint64_t sub_cap;
 };
 
 }  // namespace
@@ -866,6 +1018,8 @@ struct aceapex_decoder {
   uint32_t off_cap = 0, len_cap = 0;
   int copy_grid = 0;
   int bulk_rounds = 4;
+  int fill_round = 1, fill_tail = 0;
+  int tail_chunks = 1;
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool events_ok = false;
@@ -888,8 +1042,13 @@ Layout make_layout(const aceapex_decoder& d) {
   L.tok = at, at = align256(at + 16 * T);
   L.cov = at, at = align256(at + 8 * T);
   L.done = at, at = align256(at + T);
-  L.list0 = at, at = align256(at + 4 * T);
-  L.list1 = at, at = align256(at + 4 * T);
+  L.counts = at, at = align256(at + 4ull * 3 * kSub * kCounterStride);
+  // a workgroup appends at most what it visits: ceil(T / kSub) plus one
+  // launch-wide stride of slack per sublist
+  L.sub_cap = (T + kSub - 1) / kSub + uint64_t(kCopyThreads) * ((kMaxRoundGrid + kSub - 1) / kSub + 1);
+  L.list0 = at, at = align256(at + 4 * kSub * L.sub_cap);
+  L.list1 = at, at = align256(at + 4 * kSub * L.sub_cap);
+  L.llist = at, at = align256(at + 4 * T);
   L.total = at;
   return L;
 }
@@ -1020,6 +1179,15 @@ int aceapex_decoder_set_option(aceapex_decoder* d, int option, int64_t value) {
       if (value < 1 || value > 250) return ax::fail(AX_E_ARG, "bulk rounds must be in [1, 250]");
       d->bulk_rounds = int(value);
       return AX_OK;
+    case AX_OPT_TAIL_CHUNKS:
+      if (value < 1 || value > 64) return ax::fail(AX_E_ARG, "tail chunks must be in [1, 64]");
+      d->tail_chunks = int(value);
+      return AX_OK;
+    case AX_OPT_FILL_ROUNDS:
+    case AX_OPT_FILL_TAIL:
+      if (value < 0 || value > 1) return ax::fail(AX_E_ARG, "fill mode must be 0 or 1");
+      (option == AX_OPT_FILL_ROUNDS ? d->fill_round : d->fill_tail) = int(value);
+      return AX_OK;
     default:
       return ax::fail(AX_E_ARG, "unknown option");
   }
@@ -1070,26 +1238,31 @@ int aceapex_decode_all(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, voi
     const uint32_t ntok = uint32_t(t1 - t0);
     if (ntok) {
       uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(w + L.list0), reinterpret_cast<uint32_t*>(w + L.list1)};
+      uint32_t* counts = reinterpret_cast<uint32_t*>(w + L.counts);
+      auto cset = [&](int r) { return counts + (r % 3) * kSub * kCounterStride; };
       const uint64_t* mpre_dev = reinterpret_cast<const uint64_t*>(d->d_arc + 64) + (nb + 1);
+      hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(256), 0, s, counts, uint32_t(3 * kSub * kCounterStride));
       CopyArgs ca{reinterpret_cast<const uint64_t*>(w + L.tok), mpre_dev, t0, uint32_t(B), ntok, b0 * B, d_out,
                   reinterpret_cast<uint32_t*>(w + L.cov), w + L.done, nullptr, lists[0], nullptr,
-                  &st->count[0], &st->count[1], 0, st, (ntok + 63) / 64, 1ull << 22,
-                  copy_mode == AX_COPY_SERIAL};
-      const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, 4096));
+                  cset(0), cset(1), uint32_t(L.sub_cap), reinterpret_cast<uint32_t*>(w + L.llist), &st->long_count,
+                  0, st, (ntok + 63) / 64, 1ull << 22,
+                  copy_mode == AX_COPY_SERIAL, d->fill_round, d->fill_tail, uint32_t(d->tail_chunks)};
+      const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
       hipLaunchKernelGGL(k_round<true>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
+      hipLaunchKernelGGL(k_long, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
       for (int r = 1; r < d->bulk_rounds; ++r) {
         ca.round = uint32_t(r);
         ca.list_in = lists[(r - 1) & 1];
         ca.list_out = lists[r & 1];
-        ca.cnt_in = &st->count[(r - 1) % 3];
-        ca.cnt_out = &st->count[r % 3];
-        ca.cnt_clear = &st->count[(r + 1) % 3];
+        ca.cnt_in = cset(r - 1);
+        ca.cnt_out = cset(r);
+        ca.cnt_clear = cset(r + 1);
         // later rounds see the previous round's leftovers only: a smaller grid
         hipLaunchKernelGGL(k_round<false>, dim3(std::min<uint32_t>(grid, 512)), dim3(kCopyThreads), 0, s, ca);
       }
       ca.round = uint32_t(d->bulk_rounds);
-      const uint32_t tgrid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads,
-                                                         uint64_t(d->copy_grid)));
+      const uint64_t waves = (ntok + 64ull * d->tail_chunks - 1) / (64ull * d->tail_chunks);
+      const uint32_t tgrid = uint32_t(std::min<uint64_t>((waves + 3) / 4, uint64_t(d->copy_grid)));
       hipLaunchKernelGGL(k_tail, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);
     }
     if (timed && last) (void)hipEventRecord(d->ev[3], s);
