@@ -11,6 +11,7 @@ Prints one JSON line.  The archive is generated and encoded on the host first
 original before timing.
 """
 import argparse
+import concurrent.futures as cf
 import json
 import os
 import sys
@@ -37,7 +38,9 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="dna254", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="dna254", choices=sorted(WORKLOADS) + ["batch"])
+    ap.add_argument("--batch-count", type=int, default=4096, help="archives in the batched workload")
+    ap.add_argument("--autotune", action="store_true", help="batched workload: tune knobs per size class")
     ap.add_argument("--copy", default="periodic", choices=["periodic", "serial"])
     ap.add_argument("--no-rep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -67,11 +70,128 @@ def cpu_baseline(arc, n_bytes):
             "sample": f"whole archive ({n_bytes} B), median of 3 single-threaded oracle decodes, {t:.2f} s each"}
 
 
+# ------------------------------------------------- batched workload (config 4)
+#
+# One plan decoding every archive (launch sequence captured as a hipGraph,
+# optionally autotuned per size class) against the plain per-archive decode
+# looped over the same archives on the same stream.
+
+CLASSES = [(0, 1 << 20), (1 << 20, 8 << 20), (8 << 20, 1 << 62)]  # size classes for the autotuner
+
+
+def _make(i, size, kind):
+    import xxhash
+
+    import synth
+    import paper_2608_10188_amd as ax
+
+    x = synth.dna(size, 1000 + i) if kind == 0 else synth.text(size, 1000 + i)
+    h = xxhash.xxh3_64_intdigest(x.tobytes())
+    arc = ax.encode(x, threads=1)
+    return arc, h, size
+
+
+def run_batch(args, log):
+    import torch
+    import xxhash
+
+    import synth
+    import paper_2608_10188_amd as ax
+    from paper_2608_10188_amd import autotune
+
+    count = args.batch_count
+    sizes, kinds = synth.batch_plan(count, 4)
+    t0 = time.time()
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as pool:
+        made = list(pool.map(_make, range(count), [int(v) for v in sizes], [int(k) for k in kinds]))
+    total = sum(m[2] for m in made)
+    comp = sum(m[0].size for m in made)
+    log(f"{count} archives, {total} B decoded, {comp} B compressed, built in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    decs, outs = [], []
+    for arc, h, n in made:
+        d = ax.Decoder(arc, torch.from_numpy(arc).to(dev))
+        decs.append(d)
+        outs.append(torch.empty(max(16, n), dtype=torch.uint8, device=dev))
+    batch = ax.Batch(decs, outs)
+    work = batch.workspace()
+    log(f"batch plan: workspace {batch.workspace_bytes / 2**30:.2f} GiB")
+
+    # correctness (poisoned outputs), outside the timed region
+    for o in outs:
+        o.fill_(0xCC)
+    batch.decode()
+    err, bad = batch.status()
+    bad_archives = 0
+    for (arc, h, n), o in zip(made, outs):
+        if xxhash.xxh3_64_intdigest(o[:n].cpu().numpy().tobytes()) != h:
+            bad_archives += 1
+    if err or bad_archives:
+        print(json.dumps({"metric": "batched decoded GB/s", "value": None, "error": f"status {err}, {bad_archives} bad"}))
+        raise SystemExit(1)
+
+    def time_it(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    tuned = {}
+    if args.autotune:
+        # one plan per size class, each tuned on its own archives
+        class_plans = []
+        for lo, hi in CLASSES:
+            idx = [i for i, m in enumerate(made) if lo <= m[2] < hi]
+            if not idx:
+                continue
+            cb = ax.Batch([decs[i] for i in idx], [outs[i] for i in idx])
+            cw = cb.workspace()
+            best, table = autotune.tune(cb, lambda cb=cb, cw=cw: cb.decode(work=cw), [outs[i] for i in idx])
+            tuned[f"{lo}-{hi}"] = {"archives": len(idx), "best": {str(k): v for k, v in best.items()},
+                                   "ms": [round(t[1], 3) for t in table if t[2]], "all_identical": all(t[2] for t in table)}
+            class_plans.append((cb, cw))
+        batched_ms = time_it(lambda: [cb.decode(work=cw) for cb, cw in class_plans], args.steps, args.warmup)
+    else:
+        batch.set_option(ax.OPT_GRAPH, 1)
+        batched_ms = time_it(lambda: batch.decode(work=work), args.steps, args.warmup)
+    err, _ = batch.status()
+
+    # plain decode looped over the archives on the same stream
+    ws = max(d.workspace_bytes for d in decs)
+    shared = torch.empty(max(256, ws), dtype=torch.uint8, device=dev)
+    loop_steps = max(1, min(args.steps, 3))
+    loop_ms = time_it(lambda: [d.decode_all(out=o, work=shared) for d, o in zip(decs, outs)], loop_steps, 1)
+    err2, _ = ax.workspace_status(shared)
+
+    res = {
+        "metric": "batched decoded GB/s (4096 archives, 64 KiB-64 MiB, 60% DNA / 40% text)",
+        "value": round(total / (batched_ms / 1e3) / 1e9, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(batched_ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"batch of {count} archives", "n_bytes": total, "archive_bytes": comp,
+                   "autotuned": bool(args.autotune)},
+        "plain_loop_gbs": round(total / (loop_ms / 1e3) / 1e9, 3), "plain_loop_ms": round(loop_ms, 3),
+        "speedup_vs_plain_loop": round(loop_ms / batched_ms, 3), "status": [err, err2],
+        "autotune": tuned or None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batch":
+        run_batch(args, log)
+        return
     import torch
     import xxhash
 

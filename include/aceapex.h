@@ -163,8 +163,12 @@ enum { AX_OPT_BULK_ROUNDS = 1 };
 enum { AX_OPT_FILL_ROUNDS = 2, AX_OPT_FILL_TAIL = 3 };
 /*   AX_OPT_TAIL_CHUNKS  consecutive 64-token chunks a wave of the persistent
  *     launch takes per ticket, in [1, 64] (default 1): fewer tickets (one
- *     global counter) against less overlap of dependent chunks. */
-enum { AX_OPT_TAIL_CHUNKS = 4 };
+ *     global counter) against less overlap of dependent chunks.
+ *   AX_OPT_GRAPH  1 = capture the whole launch sequence (every window, stage
+ *     and dependency-level round) as a hipGraph on the first decode and
+ *     replay it afterwards (re-captured when the workspace, copy mode or an
+ *     option changes); stage timing is not recorded in this mode. */
+enum { AX_OPT_TAIL_CHUNKS = 4, AX_OPT_GRAPH = 5 };
 int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
 
 /* Read the device status word of a workspace after the work queued on
@@ -172,6 +176,34 @@ int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
  * *bad_block is the first failing block (or ~0). */
 int aceapex_decoder_status(aceapex_decoder* dec, void* d_work, void* stream, int32_t* dev_err,
                            uint64_t* bad_block);
+/* The same for any workspace (decode, batch or range). */
+int aceapex_workspace_status(void* d_work, void* stream, int32_t* dev_err, uint64_t* bad_block);
+
+/* --------------------------------------------------------------- batch --- */
+
+/* Batched decode: many whole archives in one plan.  All blocks of all jobs
+ * are cut into windows and every window runs as one sequence of launches
+ * (entropy, parse, match layer) over device work lists, so the number of
+ * launches does not grow with the number of archives; with AX_OPT_GRAPH the
+ * whole sequence is one captured graph.  Each job's bytes go to its d_out
+ * (16-byte aligned, out_cap >= its decoded size), fixed at creation. */
+typedef struct {
+  aceapex_decoder* dec;
+  uint8_t* d_out;
+  uint64_t out_cap;
+} aceapex_job;
+
+typedef struct aceapex_batch aceapex_batch;
+
+int aceapex_batch_create(const aceapex_job* jobs, uint32_t n, aceapex_batch** out);
+void aceapex_batch_destroy(aceapex_batch* batch);
+int aceapex_batch_workspace(const aceapex_batch* batch, uint64_t* bytes);
+int aceapex_batch_set_option(aceapex_batch* batch, int option, int64_t value);
+int aceapex_batch_set_timing(aceapex_batch* batch, int enable);
+int aceapex_batch_stage_ms(aceapex_batch* batch, float* ans_ms, float* parse_ms, float* copy_ms);
+/* Decode every job; asynchronous on `stream`; status via
+ * aceapex_workspace_status. */
+int aceapex_decode_batch(aceapex_batch* batch, void* d_work, uint64_t work_len, int copy_mode, void* stream);
 
 #ifdef __cplusplus
 }

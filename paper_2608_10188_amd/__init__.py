@@ -23,8 +23,10 @@ EXPORTS = [
     "aceapex_encode", "aceapex_read_info", "aceapex_decoder_create", "aceapex_decoder_destroy",
     "aceapex_decoder_info", "aceapex_decoder_workspace", "aceapex_decode_all", "aceapex_decoder_stage_ms",
     "aceapex_decoder_set_timing", "aceapex_decoder_status", "aceapex_decoder_set_option",
+    "aceapex_workspace_status", "aceapex_batch_create", "aceapex_batch_destroy", "aceapex_batch_workspace",
+    "aceapex_batch_set_option", "aceapex_batch_set_timing", "aceapex_batch_stage_ms", "aceapex_decode_batch",
 ]
-OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS = 1, 2, 3, 4
+OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH = 1, 2, 3, 4, 5
 
 
 class AceapexError(RuntimeError):
@@ -52,6 +54,10 @@ class Info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "n_bytes", "n_blocks", "archive_bytes", "header_bytes", "payload_bytes", "n_matches", "xxh3")] + [
         (n, ctypes.c_uint32) for n in ("block_size", "min_match", "flags", "depth_cap")]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("dec", ctypes.c_void_p), ("d_out", ctypes.c_void_p), ("out_cap", ctypes.c_uint64)]
 
 
 def _load():
@@ -82,6 +88,15 @@ def _load():
     L.aceapex_decoder_set_timing.argtypes = [vp, ctypes.c_int]
     L.aceapex_decoder_status.argtypes = [vp, vp, vp, P(ctypes.c_int32), P(u64)]
     L.aceapex_decoder_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
+    L.aceapex_workspace_status.argtypes = [vp, vp, P(ctypes.c_int32), P(u64)]
+    L.aceapex_batch_create.argtypes = [P(Job), ctypes.c_uint32, P(vp)]
+    L.aceapex_batch_destroy.argtypes = [vp]
+    L.aceapex_batch_destroy.restype = None
+    L.aceapex_batch_workspace.argtypes = [vp, P(u64)]
+    L.aceapex_batch_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
+    L.aceapex_batch_set_timing.argtypes = [vp, ctypes.c_int]
+    L.aceapex_batch_stage_ms.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float)]
+    L.aceapex_decode_batch.argtypes = [vp, vp, u64, ctypes.c_int, vp]
     _lib = L
     return L
 
@@ -211,3 +226,67 @@ class Decoder:
         _check(_load().aceapex_decoder_stage_ms(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(c)),
                "stage_ms")
         return a.value, p.value, c.value
+
+
+def workspace_status(work, stream=None):
+    err = ctypes.c_int32()
+    bad = ctypes.c_uint64()
+    _check(_load().aceapex_workspace_status(ctypes.c_void_p(work.data_ptr()), _stream_ptr(stream), ctypes.byref(err),
+                                            ctypes.byref(bad)), "workspace_status")
+    return err.value, bad.value
+
+
+class Batch:
+    """Many whole archives decoded by one plan (aceapex_decode_batch).
+
+    decoders: list of Decoder; outs: list of CUDA uint8 tensors (one per
+    decoder, at least its decoded size)."""
+
+    def __init__(self, decoders, outs):
+        n = len(decoders)
+        jobs = (Job * max(1, n))()
+        for i, (d, o) in enumerate(zip(decoders, outs)):
+            if o.numel() < d.info.n_bytes:
+                raise ValueError("output tensor smaller than the decoded size")
+            jobs[i].dec, jobs[i].d_out, jobs[i].out_cap = d._h, o.data_ptr(), o.numel()
+        self._decoders, self._outs = list(decoders), list(outs)  # keep alive
+        self._h = ctypes.c_void_p()
+        _check(_load().aceapex_batch_create(jobs, n, ctypes.byref(self._h)), "batch_create")
+        ws = ctypes.c_uint64()
+        _check(_load().aceapex_batch_workspace(self._h, ctypes.byref(ws)), "batch_workspace")
+        self.workspace_bytes = ws.value
+        self.device = outs[0].device if outs else None
+        self._work = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.aceapex_batch_destroy(self._h)
+            self._h = None
+
+    def workspace(self):
+        import torch
+
+        if self._work is None:
+            self._work = torch.empty(max(256, self.workspace_bytes), dtype=torch.uint8, device=self.device)
+        return self._work
+
+    def set_option(self, option, value):
+        _check(_load().aceapex_batch_set_option(self._h, int(option), int(value)), "batch_set_option")
+
+    def set_timing(self, on=True):
+        _check(_load().aceapex_batch_set_timing(self._h, int(bool(on))), "batch_set_timing")
+
+    def stage_ms(self):
+        a, p, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        _check(_load().aceapex_batch_stage_ms(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(c)),
+               "batch_stage_ms")
+        return a.value, p.value, c.value
+
+    def decode(self, copy_mode=COPY_PERIODIC, stream=None, work=None):
+        w = self.workspace() if work is None else work
+        _check(_load().aceapex_decode_batch(self._h, ctypes.c_void_p(w.data_ptr()), w.numel(), int(copy_mode),
+                                            _stream_ptr(stream)), "decode_batch")
+        return self._outs
+
+    def status(self, stream=None, work=None):
+        return workspace_status(self.workspace() if work is None else work, stream)

@@ -33,6 +33,7 @@
 
 #include "aceapex.h"
 #include "ax_common.h"
+#include "engine.h"
 
 namespace {
 
@@ -57,6 +58,29 @@ struct DevStatus {
 };
 static_assert(sizeof(DevStatus) == 256, "status block is 256 bytes");
 
+// One archive of a plan (a whole-archive decode, one archive of a batch, or
+// the source closure of a range): where it is, and where its bytes go.
+struct JobDev {
+  const uint8_t* arc;   // device archive
+  uint8_t* out;         // decoded bytes at the archive's absolute positions
+  uint64_t payload_at;  // header + index bytes
+  uint64_t n_bytes, nb;
+  uint32_t B, mm;
+};
+
+// One block of a window.  Window order is (job, block) ascending, and the
+// window's tokens are stored block after block in that order.
+struct WinBlock {
+  uint64_t b;       // block index in its archive
+  uint32_t job;
+  uint32_t tok;     // window index of the block's first token
+  uint32_t first;   // window index of this job's first block in the window
+  uint32_t count;   // blocks of this job in the window
+};
+
+__device__ inline uint32_t job_off_cap(const JobDev& j) { return (10u * (j.B / j.mm + 1) + 15u) & ~15u; }
+__device__ inline uint32_t job_len_cap(const JobDev& j) { return 3u * j.B; }
+
 __device__ inline void report(DevStatus* st, int code, uint64_t block) {
   if (atomicCAS(&st->err, 0, code) == 0) atomicExch(&st->bad_block, (unsigned long long)block);
 }
@@ -73,13 +97,12 @@ __device__ inline uint64_t ld64(const uint8_t* p) { return *reinterpret_cast<con
 // ------------------------------------------------------------------ k_ans --
 
 struct AnsArgs {
-  const uint8_t* arc;        // archive base
-  uint64_t payload_at;       // byte offset of the payload in the archive
-  uint64_t first_block;      // window start
+  const JobDev* jobs;
+  const WinBlock* wbl;       // this window's blocks
   uint32_t n_items;          // blocks in this window
-  uint32_t B;
-  uint8_t* lit;              // scratch, B per slot
-  uint8_t* cmd;              // scratch, B per slot
+  uint32_t slot_b;           // scratch slot stride of the literal and command streams
+  uint8_t* lit;              // scratch, slot_b per slot
+  uint8_t* cmd;              // scratch, slot_b per slot
   uint8_t* off;              // scratch, off_cap per slot
   uint8_t* len;              // scratch, len_cap per slot
   uint32_t off_cap, len_cap;
@@ -107,18 +130,20 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
 
   const uint32_t item = blockIdx.x % a.n_items;
   const uint32_t stream = blockIdx.x / a.n_items;  // 0 LIT, 1 LEN, 2 OFF, 3 CMD
-  const uint64_t b = a.first_block + item;
+  const WinBlock wb = a.wbl[item];
+  const JobDev& J = a.jobs[wb.job];
+  const uint64_t b = wb.b;
   const uint32_t lane = lane_id();
-  uint8_t* const outs[4] = {a.lit + uint64_t(item) * a.B, a.len + uint64_t(item) * a.len_cap,
-                            a.off + uint64_t(item) * a.off_cap, a.cmd + uint64_t(item) * a.B};
-  const uint32_t caps[4] = {a.B, a.len_cap, a.off_cap, a.B};
+  uint8_t* const outs[4] = {a.lit + uint64_t(item) * a.slot_b, a.len + uint64_t(item) * a.len_cap,
+                            a.off + uint64_t(item) * a.off_cap, a.cmd + uint64_t(item) * a.slot_b};
+  const uint32_t caps[4] = {J.B, job_len_cap(J), job_off_cap(J), J.B};
   uint8_t* out = outs[stream];
   const uint32_t cap = caps[stream];
   uint32_t* nsym = a.nsym + 4 * item + stream;
 
-  const uint64_t* idx = reinterpret_cast<const uint64_t*>(a.arc + 64);
+  const uint64_t* idx = reinterpret_cast<const uint64_t*>(J.arc + 64);
   const uint64_t o0 = idx[b], o1 = idx[b + 1];
-  const uint8_t* blk = a.arc + a.payload_at + o0;
+  const uint8_t* blk = J.arc + J.payload_at + o0;
   const uint64_t blen = o1 - o0;  // validated on the host: >= 16, 16-aligned
   uint64_t at = 16;
   for (uint32_t k = 0; k < stream; ++k) at += ld32(blk + 4 * k);
@@ -226,8 +251,8 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
   uint32_t x = lane < K ? ld32(rec + states_at + 4 * lane) : ax::kRansLow;
   bad = x < ax::kRansLow;
   auto fetch = [&](uint32_t i) -> uint32_t { return i < nw ? uint32_t(words[i]) : 0u; };
-  uint32_t base = 0;  // window: wa = words[base+lane], wb = words[base+64+lane], wc = words[base+128+lane]
-  uint32_t wa = fetch(lane), wb = fetch(64 + lane), wc = fetch(128 + lane);
+  uint32_t base = 0;  // window: wa = words[base+lane], w1 = words[base+64+lane], w2 = words[base+128+lane]
+  uint32_t wa = fetch(lane), w1 = fetch(64 + lane), w2 = fetch(128 + lane);
   uint32_t ptr = 0;
   const uint32_t steps = (n + K - 1) / K;
   uint32_t i = lane;
@@ -241,7 +266,7 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
     const uint64_t m = __ballot(need);
     const uint32_t q = ptr - base + lanes_below(m);  // < 128
     const uint32_t va = __builtin_amdgcn_ds_bpermute(int((q & 63) << 2), int(wa));
-    const uint32_t vb = __builtin_amdgcn_ds_bpermute(int((q & 63) << 2), int(wb));
+    const uint32_t vb = __builtin_amdgcn_ds_bpermute(int((q & 63) << 2), int(w1));
     const uint32_t w = q < 64 ? va : vb;
     if (act) {
       x = need ? ((xn << 16) | w) : xn;
@@ -250,9 +275,9 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
     ptr += __popcll(m);
     if (ptr - base >= 64) {
       base += 64;
-      wa = wb;
-      wb = wc;
-      wc = fetch(base + 128 + lane);
+      wa = w1;
+      w1 = w2;
+      w2 = fetch(base + 128 + lane);
     }
   }
   bad |= lane < K && x != ax::kRansLow;
@@ -266,19 +291,17 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
 // ---------------------------------------------------------------- k_parse --
 
 struct ParseArgs {
-  const uint8_t* arc;
-  uint64_t n_bytes;
-  uint64_t first_block;
+  const JobDev* jobs;
+  const WinBlock* wbl;
   uint32_t n_items;
-  uint32_t B, mm;
+  uint32_t n_tok;            // tokens in the window
+  uint32_t slot_b;
   const uint8_t *lit, *cmd, *off, *len;
   uint32_t off_cap, len_cap;
   const uint32_t* nsym;
-  uint64_t tok_first;        // cumulative match count at the window start
-  uint64_t tok_count;        // tokens in the window
   uint64_t* tok;             // 2 u64 per token: src, dst | (len-1) << 48
+  uint32_t* tblk;            // per token: its window block
   uint8_t* done;             // per token: kPending until the match layer copies it
-  uint8_t* out;              // decoded bytes (absolute positions)
   DevStatus* st;
 };
 
@@ -446,20 +469,24 @@ __device__ bool leb_values(const uint8_t* src, uint32_t n, uint32_t* cursor, uin
 __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
   __shared__ ParseShared sh;
   const uint32_t item = blockIdx.x, t = threadIdx.x;
-  const uint64_t b = a.first_block + item;
-  const uint32_t B = a.B, mm = a.mm;
+  const WinBlock wb = a.wbl[item];
+  const JobDev& J = a.jobs[wb.job];
+  const uint64_t b = wb.b;
+  const uint32_t B = J.B, mm = J.mm;
   const uint64_t bs = b * B;
-  const uint32_t blen = uint32_t(min<uint64_t>(B, a.n_bytes - bs));
+  const uint32_t blen = uint32_t(min<uint64_t>(B, J.n_bytes - bs));
   const uint32_t n_lit = a.nsym[4 * item + 0], n_len = a.nsym[4 * item + 1];
   const uint32_t n_off = a.nsym[4 * item + 2], n_cmd = a.nsym[4 * item + 3];
-  const uint8_t* cmd = a.cmd + uint64_t(item) * B;
-  const uint8_t* lit = a.lit + uint64_t(item) * B;
+  const uint8_t* cmd = a.cmd + uint64_t(item) * a.slot_b;
+  const uint8_t* lit = a.lit + uint64_t(item) * a.slot_b;
   const uint8_t* offs = a.off + uint64_t(item) * a.off_cap;
   const uint8_t* lens = a.len + uint64_t(item) * a.len_cap;
-  const uint64_t* mpre = reinterpret_cast<const uint64_t*>(a.arc + 64) + (a.n_bytes + B - 1) / B + 1;
-  const uint64_t tok_lo = mpre[b] - a.tok_first, tok_n = mpre[b + 1] - mpre[b];
+  const uint64_t* mpre = reinterpret_cast<const uint64_t*>(J.arc + 64) + J.nb + 1;
+  const uint64_t tok_lo = wb.tok, tok_n = mpre[b + 1] - mpre[b];
 
-  if (t == 0) sh.bad = (n_lit > B || n_cmd > B || n_len > a.len_cap || n_off > a.off_cap) ? 1 : 0;
+  if (t == 0)
+    sh.bad = (n_lit > B || n_cmd > B || n_len > job_len_cap(J) || n_off > job_off_cap(J) ||
+              tok_lo + tok_n > a.n_tok) ? 1 : 0;
   // stage the offset and length streams in LDS (16-byte loads; slots are 16-aligned)
   if (n_off <= kOffStage)
     for (uint32_t k = 16 * t; k < n_off; k += 16 * kParseThreads)
@@ -542,6 +569,7 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
         uint64_t* tk = a.tok + 2 * (tok_lo + gi);
         tk[0] = src;
         tk[1] = absdst | (uint64_t(len - 1) << 48);
+        a.tblk[tok_lo + gi] = item;
         a.done[tok_lo + gi] = kPending;
       } else {
         bad = true;
@@ -597,7 +625,7 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     return;
   }
   // write the tile with 16-byte stores (match bytes are filled by the match layer)
-  uint8_t* o = a.out + bs;
+  uint8_t* o = J.out + bs;
   const uint32_t full = blen & ~15u;
   for (uint32_t k = 16 * t; k < full; k += 16 * kParseThreads)
     *reinterpret_cast<uint4*>(o + k) = *reinterpret_cast<const uint4*>(sh.tile + k);
@@ -607,13 +635,12 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
 // ------------------------------------------------------------ match layer --
 
 struct CopyArgs {
-  const uint64_t* tok;       // window tokens in output order
-  const uint64_t* mpre;      // archive index: cumulative match count per block
-  uint64_t tok_first;        // cumulative match count at the window start
-  uint32_t B;
+  const JobDev* jobs;
+  const WinBlock* wbl;
+  uint32_t n_items;
+  const uint64_t* tok;       // window tokens in (job, output) order
+  const uint32_t* tblk;      // per token: its window block
   uint32_t n_tok;
-  uint64_t win_lo;           // bytes below are final
-  uint8_t* out;
   uint32_t* cov;             // per token: first covering token, count
   uint8_t* done;             // per token: round that copied it, or kPending
   const uint32_t* list_in;   // pending tokens of the previous round: kSub sublists of sub_cap
@@ -640,21 +667,39 @@ __device__ inline void token_at(const uint64_t* tok, uint64_t t, uint64_t& src, 
   len = uint32_t(w >> 48) + 1;
 }
 
-// Tokens [lo, lo+cnt) are those whose destinations meet [s0, s1).  Tokens
-// are disjoint and sorted by destination, and the archive index gives the
-// token range of every block, so the search runs inside the block holding s0.
-__device__ inline void find_cover(const CopyArgs& a, uint64_t s0, uint64_t s1, uint32_t& lo, uint32_t& cnt) {
-  const uint64_t sb = s0 / a.B;
-  uint32_t x = uint32_t(a.mpre[sb] - a.tok_first), y = uint32_t(a.mpre[sb + 1] - a.tok_first);
-  while (x < y) {  // first token ending after s0 (or the next block's first token)
+// Tokens [lo, lo+cnt) are those whose destinations meet [s0, s1) of the
+// job of window block wb.  Tokens are disjoint and sorted by destination
+// within a job, and a job's window blocks are contiguous and ascending, so
+// the search runs over the job's window blocks, then inside the block that
+// holds s0.  Source bytes outside every window block of the job were
+// written by an earlier window or are not decoded by this plan (a range
+// decode reads only bytes whose blocks it holds), so nothing waits on them.
+__device__ inline void find_cover(const CopyArgs& a, const WinBlock& wb, uint32_t B, uint64_t s0, uint64_t s1,
+                                  uint32_t& lo, uint32_t& cnt) {
+  const uint64_t sb = s0 / B;
+  const uint32_t job_end = wb.first + wb.count;
+  uint32_t x = wb.first, y = job_end;
+  while (x < y) {  // first window block of the job with b >= sb
     const uint32_t mid = (x + y) >> 1;
-    const uint64_t w = a.tok[2 * uint64_t(mid) + 1];
-    if ((w & ((1ull << 48) - 1)) + (w >> 48) + 1 <= s0) x = mid + 1; else y = mid;
+    if (a.wbl[mid].b < sb) x = mid + 1; else y = mid;
   }
-  lo = x;
+  const uint32_t end_tok = job_end < a.n_items ? a.wbl[job_end].tok : a.n_tok;
+  uint32_t p = x < job_end ? a.wbl[x].tok : end_tok;
+  if (x < job_end && a.wbl[x].b == sb) {  // first token of block x ending after s0
+    uint32_t q = x + 1 < a.n_items ? a.wbl[x + 1].tok : a.n_tok;
+    while (p < q) {
+      const uint32_t mid = (p + q) >> 1;
+      const uint64_t w = a.tok[2 * uint64_t(mid) + 1];
+      if ((w & ((1ull << 48) - 1)) + (w >> 48) + 1 <= s0) p = mid + 1; else q = mid;
+    }
+  }
+  lo = p;
   cnt = 0;
-  while (x + cnt < a.n_tok && (a.tok[2 * uint64_t(x + cnt) + 1] & ((1ull << 48) - 1)) < s1) ++cnt;
+  while (p + cnt < end_tok && (a.tok[2 * uint64_t(p + cnt) + 1] & ((1ull << 48) - 1)) < s1) ++cnt;
 }
+
+// The output base of token t's archive.
+__device__ inline uint8_t* token_out(const CopyArgs& a, uint32_t t) { return a.jobs[a.wbl[a.tblk[t]].job].out; }
 
 template <bool COH>
 __device__ inline uint8_t ldb(const uint8_t* p) {
@@ -732,6 +777,7 @@ struct FillStage {
   uint32_t len[64];
   uint64_t dst[64];
   uint64_t src[64];
+  uint8_t* out[64];
 };
 
 constexpr uint32_t kFillBytes = 8;  // consecutive bytes per lane per pass
@@ -757,7 +803,8 @@ __device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64
     while (lm) {
       const int l = __builtin_ctzll(lm);
       lm &= lm - 1;
-      fill_wave<COH>(out, __shfl((unsigned long long)dst, l, 64), __shfl((unsigned long long)src, l, 64),
+      uint8_t* const o = reinterpret_cast<uint8_t*>(__shfl((unsigned long long)reinterpret_cast<uintptr_t>(out), l, 64));
+      fill_wave<COH>(o, __shfl((unsigned long long)dst, l, 64), __shfl((unsigned long long)src, l, 64),
                      __shfl(len, l, 64), lane);
     }
     return;
@@ -769,6 +816,7 @@ __device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64
   fs.len[lane] = mine;
   fs.dst[lane] = dst;
   fs.src[lane] = src;
+  fs.out[lane] = out;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   for (uint32_t base = 0; base < total; base += 64 * kFillBytes) {
@@ -783,6 +831,7 @@ __device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64
         if (fs.end[l + step - 1] <= f0) l += step;
       uint32_t e = fs.end[l], start = e - fs.len[l];
       uint64_t d = fs.dst[l], sr = fs.src[l], dist = d - sr;
+      uint8_t* o = fs.out[l];
       uint64_t k = f0 - start;  // < 2^16: a token lies inside one block
       uint64_t j = dist > k ? k : uint64_t(uint32_t(k) % uint32_t(dist));
 #pragma unroll
@@ -793,18 +842,20 @@ __device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64
           e = fs.end[l];
           start = e - fs.len[l];
           d = fs.dst[l], sr = fs.src[l], dist = d - sr;
+          o = fs.out[l];
           k = 0, j = 0;
         }
-        at[q] = sr + j;
-        to[q] = f < total ? d + k : ~0ull;
+        at[q] = reinterpret_cast<uint64_t>(o + sr + j);
+        to[q] = f < total ? reinterpret_cast<uint64_t>(o + d + k) : ~0ull;
         ++k;
         if (++j == dist) j = 0;
       }
 #pragma unroll
-      for (uint32_t q = 0; q < kFillBytes; ++q) v[q] = to[q] != ~0ull ? ldb<COH>(out + at[q]) : uint8_t(0);
+      for (uint32_t q = 0; q < kFillBytes; ++q)
+        v[q] = to[q] != ~0ull ? ldb<COH>(reinterpret_cast<const uint8_t*>(at[q])) : uint8_t(0);
 #pragma unroll
       for (uint32_t q = 0; q < kFillBytes; ++q)
-        if (to[q] != ~0ull) stb<COH>(out + to[q], v[q]);
+        if (to[q] != ~0ull) stb<COH>(reinterpret_cast<uint8_t*>(to[q]), v[q]);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -853,12 +904,15 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     }
     uint64_t src = 0, dst = 0;
     uint32_t len = 0, lo = 0, cnt = 0;
+    uint8_t* out = nullptr;
     if (act) {
       token_at(a.tok, t, src, dst, len);
+      const WinBlock wb = a.wbl[a.tblk[t]];
+      const JobDev& J = a.jobs[wb.job];
+      out = J.out;
       if (FIRST) {
         const uint64_t dist = dst - src;
-        const uint64_t s1 = src + (dist < len ? dist : len);
-        if (s1 > a.win_lo) find_cover(a, src < a.win_lo ? a.win_lo : src, s1, lo, cnt);
+        find_cover(a, wb, J.B, src, src + (dist < len ? dist : len), lo, cnt);
         a.cov[2 * t] = lo;
         a.cov[2 * t + 1] = cnt;
       } else {
@@ -878,7 +932,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
       at = __shfl(at, 0, 64);
       if (split) a.long_list[at + lanes_below(sm)] = t;
     }
-    fill_ready<false>(a.out, ready && !split, dst, src, len, a.serial, FIRST ? a.fill_round : a.fill_tail, fs);
+    fill_ready<false>(out, ready && !split, dst, src, len, a.serial, FIRST ? a.fill_round : a.fill_tail, fs);
     if (ready && !split) a.done[t] = uint8_t(a.round);
     const bool left = act && !ready;
     const uint64_t m = __ballot(left);
@@ -902,6 +956,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_long(CopyArgs a) {
     uint64_t src, dst;
     uint32_t len;
     token_at(a.tok, t, src, dst, len);
+    uint8_t* const out = token_out(a, t);
     const uint64_t dist = dst - src;
     const uint64_t step = uint64_t(kCopyThreads) % dist;
     uint64_t j = threadIdx.x % dist;
@@ -915,10 +970,10 @@ __global__ __launch_bounds__(kCopyThreads) void k_long(CopyArgs a) {
       }
       uint8_t v[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = (k0 + kCopyThreads * q < len) ? a.out[src + idx[q]] : uint8_t(0);
+      for (int q = 0; q < 16; ++q) v[q] = (k0 + kCopyThreads * q < len) ? out[src + idx[q]] : uint8_t(0);
 #pragma unroll
       for (int q = 0; q < 16; ++q)
-        if (k0 + kCopyThreads * q < len) a.out[dst + k0 + kCopyThreads * q] = v[q];
+        if (k0 + kCopyThreads * q < len) out[dst + k0 + kCopyThreads * q] = v[q];
     }
     __syncthreads();
     if (threadIdx.x == 0) a.done[t] = 0;
@@ -949,8 +1004,10 @@ __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
       if (!__ballot(pending)) continue;
       uint64_t src = 0, dst = 0;
       uint32_t len = 0, lo = 0, cnt = 0;
+      uint8_t* out = nullptr;
       if (pending) {
         token_at(a.tok, t, src, dst, len);
+        out = token_out(a, t);
         lo = a.cov[2 * t];
         cnt = a.cov[2 * t + 1];
       }
@@ -961,7 +1018,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
           ready = __hip_atomic_load(a.done + lo + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kPending;
         if (__ballot(ready)) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-          fill_ready<true>(a.out, ready, dst, src, len, a.serial, a.fill_tail, fs);
+          fill_ready<true>(out, ready, dst, src, len, a.serial, a.fill_tail, fs);
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the bytes are out before the flags
           if (ready) __hip_atomic_store(a.done + t, uint8_t(a.round), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1001,45 +1058,67 @@ __global__ void k_clear_u32(uint32_t* p, uint32_t n) {
 
 inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
+}  // namespace
+
+namespace ax {
+
 struct Layout {
-  uint64_t status, nsym, lit, cmd, off, len, tok, cov, done, counts, list0, list1, llist, total;
+  uint64_t status, nsym, lit, cmd, off, len, tok, tblk, cov, done, counts, list0, list1, llist, total;
   uint64_t sub_cap;
 };
 
-}  // namespace
-
-struct aceapex_decoder {
-  aceapex_info info{};
-  std::vector<uint64_t> offs, mpre;
-  const uint8_t* d_arc = nullptr;
-  uint64_t arc_len = 0;
-  uint32_t window_blocks = 0;  // blocks per decode window
-  uint64_t window_tok_max = 0; // most tokens in any window
-  uint32_t off_cap = 0, len_cap = 0;
-  int copy_grid = 0;
-  int bulk_rounds = 4;
-  int fill_round = 1, fill_tail = 0;
-  int tail_chunks = 1;
-  bool timing = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool events_ok = false;
+// A decode plan: jobs (archives and where their bytes go), cut into windows
+// of at most kWindowBlocks blocks.  A window's sources lie in earlier windows
+// or inside it, so windows run one after another with bounded scratch.
+struct Plan {
+  std::vector<JobDev> jobs;
+  std::vector<WinBlock> wbl;
+  struct Win {
+    uint64_t at;       // first WinBlock
+    uint32_t items;    // blocks
+    uint32_t tok;      // tokens
+  };
+  std::vector<Win> wins;
+  uint32_t max_items = 0, max_tok = 0, slot_b = 0, off_cap = 0, len_cap = 0;
+  uint64_t out_bytes = 0, n_tokens = 0;
+  void* d_mem = nullptr;
+  JobDev* d_jobs = nullptr;
+  WinBlock* d_wbl = nullptr;
+  JobDev* h_pinned = nullptr;  // staging for refreshing output pointers
+  std::vector<uint8_t*> dev_out;  // output pointers as last uploaded
   Layout lay{};
+  PlanOptions opt{};
+  int copy_grid = 1;
+  bool timing = false, events_ok = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t graph = nullptr;
+  hipGraph_t graph_def = nullptr;
+  void* graph_work = nullptr;
+  int graph_mode = -1;
+  hipStream_t cap_stream = nullptr;
+  ~Plan() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (graph_def) (void)hipGraphDestroy(graph_def);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (d_mem) (void)hipFree(d_mem);
+    if (h_pinned) (void)hipHostFree(h_pinned);
+  }
 };
 
-namespace {
-
-Layout make_layout(const aceapex_decoder& d) {
+static Layout make_layout(const Plan& P) {
   Layout L{};
-  const uint64_t W = d.window_blocks, B = d.info.block_size;
+  const uint64_t W = std::max<uint32_t>(1, P.max_items), T = std::max<uint32_t>(1, P.max_tok);
   uint64_t at = 0;
   L.status = at, at = align256(at + sizeof(DevStatus));
   L.nsym = at, at = align256(at + 16 * W);
-  L.lit = at, at = align256(at + W * B);
-  L.cmd = at, at = align256(at + W * B);
-  L.off = at, at = align256(at + W * d.off_cap);
-  L.len = at, at = align256(at + W * d.len_cap);
-  const uint64_t T = std::max<uint64_t>(1, d.window_tok_max);
+  L.lit = at, at = align256(at + W * P.slot_b);
+  L.cmd = at, at = align256(at + W * P.slot_b);
+  L.off = at, at = align256(at + W * P.off_cap);
+  L.len = at, at = align256(at + W * P.len_cap);
   L.tok = at, at = align256(at + 16 * T);
+  L.tblk = at, at = align256(at + 4 * T);
   L.cov = at, at = align256(at + 8 * T);
   L.done = at, at = align256(at + T);
   L.counts = at, at = align256(at + 4ull * 3 * kSub * kCounterStride);
@@ -1053,12 +1132,288 @@ Layout make_layout(const aceapex_decoder& d) {
   return L;
 }
 
-int hip_fail(hipError_t e, const char* what) {
+static int hip_fail(hipError_t e, const char* what) {
   (void)what;
-  return ax::fail(AX_E_HIP, hipGetErrorString(e));
+  return fail(AX_E_HIP, hipGetErrorString(e));
 }
 
-}  // namespace
+int plan_create(const std::vector<JobSpec>& specs, Plan** out) {
+  *out = nullptr;
+  Plan* P = new (std::nothrow) Plan;
+  if (!P) return fail(AX_E_NOMEM, "plan");
+  try {
+    P->jobs.resize(specs.size());
+    uint64_t gblocks = 0;
+    for (size_t j = 0; j < specs.size(); ++j) {
+      const aceapex_decoder* d = specs[j].dec;
+      const aceapex_info& I = d->info;
+      JobDev& J = P->jobs[j];
+      J.arc = d->d_arc;
+      J.out = specs[j].out;
+      J.payload_at = I.header_bytes;
+      J.n_bytes = I.n_bytes;
+      J.nb = I.n_blocks;
+      J.B = I.block_size;
+      J.mm = I.min_match;
+      P->slot_b = std::max(P->slot_b, I.block_size);
+      P->off_cap = std::max(P->off_cap, uint32_t((10 * (I.block_size / I.min_match + 1) + 15) & ~15u));
+      P->len_cap = std::max(P->len_cap, 3 * I.block_size);
+      P->out_bytes += I.n_bytes;
+      gblocks += specs[j].blocks.empty() ? I.n_blocks : specs[j].blocks.size();
+    }
+    P->wbl.reserve(gblocks);
+    // windows: consecutive (job, block) items, at most kWindowBlocks blocks
+    // and kWindowTokens tokens each
+    Plan::Win cur{0, 0, 0};
+    auto close = [&]() {
+      if (!cur.items) return;
+      // per-job extents inside the window
+      for (uint64_t i = cur.at; i < cur.at + cur.items;) {
+        uint64_t k = i;
+        while (k < cur.at + cur.items && P->wbl[k].job == P->wbl[i].job) ++k;
+        for (uint64_t m = i; m < k; ++m) {
+          P->wbl[m].first = uint32_t(i - cur.at);
+          P->wbl[m].count = uint32_t(k - i);
+        }
+        i = k;
+      }
+      P->max_items = std::max(P->max_items, cur.items);
+      P->max_tok = std::max(P->max_tok, cur.tok);
+      P->n_tokens += cur.tok;
+      P->wins.push_back(cur);
+      cur = Plan::Win{P->wbl.size(), 0, 0};
+    };
+    for (size_t j = 0; j < specs.size(); ++j) {
+      const aceapex_decoder* d = specs[j].dec;
+      const uint64_t nb = specs[j].blocks.empty() ? d->info.n_blocks : specs[j].blocks.size();
+      for (uint64_t i = 0; i < nb; ++i) {
+        const uint64_t b = specs[j].blocks.empty() ? i : specs[j].blocks[i];
+        const uint64_t nt = d->mpre[b + 1] - d->mpre[b];
+        if (cur.items == kWindowBlocks || uint64_t(cur.tok) + nt > kWindowTokens) close();
+        P->wbl.push_back(WinBlock{b, uint32_t(j), cur.tok, 0, 0});
+        cur.items++;
+        cur.tok += uint32_t(nt);
+      }
+    }
+    close();
+  } catch (const std::bad_alloc&) {
+    delete P;
+    return fail(AX_E_NOMEM, "plan tables");
+  }
+  const size_t jb = sizeof(JobDev) * std::max<size_t>(1, P->jobs.size());
+  const size_t wb = sizeof(WinBlock) * std::max<size_t>(1, P->wbl.size());
+  hipError_t e = hipMalloc(&P->d_mem, align256(jb) + wb);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&P->h_pinned), jb);
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "plan memory");
+  }
+  P->d_jobs = static_cast<JobDev*>(P->d_mem);
+  P->d_wbl = reinterpret_cast<WinBlock*>(static_cast<uint8_t*>(P->d_mem) + align256(jb));
+  if (!P->jobs.empty()) e = hipMemcpy(P->d_jobs, P->jobs.data(), sizeof(JobDev) * P->jobs.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !P->wbl.empty())
+    e = hipMemcpy(P->d_wbl, P->wbl.data(), sizeof(WinBlock) * P->wbl.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "plan upload");
+  }
+  P->dev_out.resize(P->jobs.size());
+  for (size_t j = 0; j < P->jobs.size(); ++j) P->dev_out[j] = P->jobs[j].out;
+  P->lay = make_layout(*P);
+  int dev = 0, cus = 0, occ = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_tail), kCopyThreads, 0);
+  P->copy_grid = std::max(1, cus) * std::max(1, occ);
+  *out = P;
+  return AX_OK;
+}
+
+void plan_destroy(Plan* P) { delete P; }
+uint64_t plan_workspace(const Plan* P) { return P->lay.total; }
+uint64_t plan_tokens(const Plan* P) { return P->n_tokens; }
+uint64_t plan_blocks(const Plan* P) { return P->wbl.size(); }
+
+int plan_set_out(Plan* P, size_t job, uint8_t* out) {
+  if (job >= P->jobs.size()) return fail(AX_E_ARG, "job index");
+  P->jobs[job].out = out;
+  return AX_OK;
+}
+
+int plan_set_option(Plan* P, int option, int64_t value) {
+  switch (option) {
+    case AX_OPT_BULK_ROUNDS:
+      if (value < 1 || value > 250) return fail(AX_E_ARG, "bulk rounds must be in [1, 250]");
+      P->opt.bulk_rounds = int(value);
+      break;
+    case AX_OPT_TAIL_CHUNKS:
+      if (value < 1 || value > 64) return fail(AX_E_ARG, "tail chunks must be in [1, 64]");
+      P->opt.tail_chunks = int(value);
+      break;
+    case AX_OPT_FILL_ROUNDS:
+    case AX_OPT_FILL_TAIL:
+      if (value < 0 || value > 1) return fail(AX_E_ARG, "fill mode must be 0 or 1");
+      (option == AX_OPT_FILL_ROUNDS ? P->opt.fill_round : P->opt.fill_tail) = int(value);
+      break;
+    case AX_OPT_GRAPH:
+      if (value < 0 || value > 1) return fail(AX_E_ARG, "graph must be 0 or 1");
+      P->opt.graph = int(value);
+      break;
+    default:
+      return fail(AX_E_ARG, "unknown option");
+  }
+  if (P->graph) {  // knobs are baked into a captured graph
+    (void)hipGraphExecDestroy(P->graph);
+    P->graph = nullptr;
+  }
+  return AX_OK;
+}
+
+int plan_get_option(const Plan* P, int option, int64_t* value) {
+  switch (option) {
+    case AX_OPT_BULK_ROUNDS: *value = P->opt.bulk_rounds; return AX_OK;
+    case AX_OPT_TAIL_CHUNKS: *value = P->opt.tail_chunks; return AX_OK;
+    case AX_OPT_FILL_ROUNDS: *value = P->opt.fill_round; return AX_OK;
+    case AX_OPT_FILL_TAIL: *value = P->opt.fill_tail; return AX_OK;
+    case AX_OPT_GRAPH: *value = P->opt.graph; return AX_OK;
+    default: return fail(AX_E_ARG, "unknown option");
+  }
+}
+
+int plan_set_timing(Plan* P, int enable) {
+  if (enable && !P->events_ok) {
+    for (auto& e : P->ev) {
+      hipError_t er = hipEventCreate(&e);
+      if (er != hipSuccess) return hip_fail(er, "hipEventCreate");
+    }
+    P->events_ok = true;
+  }
+  P->timing = enable != 0;
+  return AX_OK;
+}
+
+int plan_stage_ms(Plan* P, float* ans, float* parse, float* copy) {
+  if (!P->events_ok) return fail(AX_E_ARG, "timing not enabled");
+  hipError_t e = hipEventSynchronize(P->ev[3]);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  (void)hipEventElapsedTime(ans, P->ev[0], P->ev[1]);
+  (void)hipEventElapsedTime(parse, P->ev[1], P->ev[2]);
+  (void)hipEventElapsedTime(copy, P->ev[2], P->ev[3]);
+  return AX_OK;
+}
+
+// Enqueue the plan's kernels on s (also used inside a graph capture).
+static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool timed) {
+  const Layout& L = P->lay;
+  DevStatus* st = reinterpret_cast<DevStatus*>(w + L.status);
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, st);
+  for (size_t wi = 0; wi < P->wins.size(); ++wi) {
+    const Plan::Win& W = P->wins[wi];
+    const bool first = wi == 0, last = wi + 1 == P->wins.size();
+    const WinBlock* wbl = P->d_wbl + W.at;
+    hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st);
+    AnsArgs aa{P->d_jobs, wbl, W.items, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
+               P->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
+    if (timed && first) (void)hipEventRecord(P->ev[0], s);
+    hipLaunchKernelGGL(k_ans, dim3(4 * W.items), dim3(64), 0, s, aa);
+    if (timed && first) (void)hipEventRecord(P->ev[1], s);
+    ParseArgs pa{P->d_jobs, wbl, W.items, W.tok, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
+                 P->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), reinterpret_cast<uint64_t*>(w + L.tok),
+                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st};
+    hipLaunchKernelGGL(k_parse, dim3(W.items), dim3(kParseThreads), 0, s, pa);
+    if (timed && first) (void)hipEventRecord(P->ev[2], s);
+    const uint32_t ntok = W.tok;
+    if (ntok) {
+      uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(w + L.list0), reinterpret_cast<uint32_t*>(w + L.list1)};
+      uint32_t* counts = reinterpret_cast<uint32_t*>(w + L.counts);
+      auto cset = [&](int r) { return counts + (r % 3) * kSub * kCounterStride; };
+      hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(256), 0, s, counts, uint32_t(3 * kSub * kCounterStride));
+      CopyArgs ca{P->d_jobs, wbl, W.items, reinterpret_cast<const uint64_t*>(w + L.tok),
+                  reinterpret_cast<const uint32_t*>(w + L.tblk), ntok, reinterpret_cast<uint32_t*>(w + L.cov),
+                  w + L.done, nullptr, lists[0], nullptr, cset(0), cset(1), uint32_t(L.sub_cap),
+                  reinterpret_cast<uint32_t*>(w + L.llist), &st->long_count, 0, st, (ntok + 63) / 64, 1ull << 22,
+                  copy_mode == AX_COPY_SERIAL, P->opt.fill_round, P->opt.fill_tail, uint32_t(P->opt.tail_chunks)};
+      const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
+      hipLaunchKernelGGL(k_round<true>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
+      hipLaunchKernelGGL(k_long, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
+      for (int r = 1; r < P->opt.bulk_rounds; ++r) {
+        ca.round = uint32_t(r);
+        ca.list_in = lists[(r - 1) & 1];
+        ca.list_out = lists[r & 1];
+        ca.cnt_in = cset(r - 1);
+        ca.cnt_out = cset(r);
+        ca.cnt_clear = cset(r + 1);
+        // later rounds see the previous round's leftovers only: a smaller grid
+        hipLaunchKernelGGL(k_round<false>, dim3(std::min<uint32_t>(grid, 512)), dim3(kCopyThreads), 0, s, ca);
+      }
+      ca.round = uint32_t(P->opt.bulk_rounds);
+      const uint64_t waves = (ntok + 64ull * P->opt.tail_chunks - 1) / (64ull * P->opt.tail_chunks);
+      const uint32_t tgrid = uint32_t(std::min<uint64_t>((waves + 3) / 4, uint64_t(P->copy_grid)));
+      hipLaunchKernelGGL(k_tail, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);
+    }
+    if (timed && last) (void)hipEventRecord(P->ev[3], s);
+  }
+}
+
+int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s) {
+  if (!d_work) return fail(AX_E_ARG, "null workspace");
+  if (work_len < P->lay.total) return fail(AX_E_CAPACITY, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(d_work) & 255) return fail(AX_E_ARG, "workspace must be 256-byte aligned");
+  if (copy_mode != AX_COPY_PERIODIC && copy_mode != AX_COPY_SERIAL) return fail(AX_E_ARG, "bad copy mode");
+  for (size_t j = 0; j < P->jobs.size(); ++j) {
+    if (!P->jobs[j].out && P->jobs[j].n_bytes) return fail(AX_E_ARG, "job without an output buffer");
+    if (reinterpret_cast<uintptr_t>(P->jobs[j].out) & 15) return fail(AX_E_ARG, "outputs must be 16-byte aligned");
+  }
+  // refresh output pointers that changed since the last upload
+  bool stale = false;
+  for (size_t j = 0; j < P->jobs.size(); ++j) stale |= P->dev_out[j] != P->jobs[j].out;
+  if (stale) {
+    std::memcpy(P->h_pinned, P->jobs.data(), sizeof(JobDev) * P->jobs.size());
+    hipError_t e = hipMemcpyAsync(P->d_jobs, P->h_pinned, sizeof(JobDev) * P->jobs.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "job table update");
+    for (size_t j = 0; j < P->jobs.size(); ++j) P->dev_out[j] = P->jobs[j].out;
+  }
+  uint8_t* w = static_cast<uint8_t*>(d_work);
+  const bool timed = P->timing && P->events_ok;
+  if (P->opt.graph && !timed) {
+    // the launch sequence of every window and round, captured once and replayed
+    if (!P->graph || P->graph_work != d_work || P->graph_mode != copy_mode) {
+      if (P->graph) (void)hipGraphExecDestroy(P->graph), P->graph = nullptr;
+      if (P->graph_def) (void)hipGraphDestroy(P->graph_def), P->graph_def = nullptr;
+      if (!P->cap_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "capture stream");
+      }
+      hipError_t e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "graph capture");
+      enqueue(P, w, copy_mode, P->cap_stream, false);
+      e = hipStreamEndCapture(P->cap_stream, &P->graph_def);
+      if (e == hipSuccess) e = hipGraphInstantiate(&P->graph, P->graph_def, nullptr, nullptr, 0);
+      if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+      P->graph_work = d_work;
+      P->graph_mode = copy_mode;
+    }
+    hipError_t e = hipGraphLaunch(P->graph, s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return AX_OK;
+  }
+  enqueue(P, w, copy_mode, s, timed);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return AX_OK;
+}
+
+int workspace_status(void* d_work, hipStream_t s, int32_t* dev_err, uint64_t* bad_block) {
+  DevStatus hs;
+  hipError_t e = hipMemcpyAsync(&hs, d_work, sizeof(hs), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "status read");
+  *dev_err = hs.err;
+  *bad_block = hs.bad_block;
+  return AX_OK;
+}
+
+}  // namespace ax
 
 extern "C" {
 
@@ -1122,28 +1477,18 @@ int aceapex_decoder_create(const uint8_t* h, uint64_t h_len, const uint8_t* d_ar
     delete d;
     return ax::fail(AX_E_CORRUPT, "bad index");
   }
-  d->off_cap = uint32_t((10 * (B / I.min_match + 1) + 15) & ~15u);
-  d->len_cap = uint32_t(3 * B);
-  // windows of up to 32768 blocks bound the workspace for very large archives
-  d->window_blocks = uint32_t(std::min<uint64_t>(std::max<uint64_t>(nb, 1), 32768));
-  for (uint64_t b0 = 0; b0 < nb; b0 += d->window_blocks) {
-    const uint64_t b1 = std::min<uint64_t>(nb, b0 + d->window_blocks);
-    d->window_tok_max = std::max(d->window_tok_max, d->mpre[b1] - d->mpre[b0]);
+  rc = ax::plan_create({ax::JobSpec{d, nullptr, {}}}, &d->plan);
+  if (rc) {
+    delete d;
+    return rc;
   }
-  d->lay = make_layout(*d);
-  int dev = 0, cus = 0, occ = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_tail), kCopyThreads, 0);
-  d->copy_grid = std::max(1, cus) * std::max(1, occ);
   *out = d;
   return AX_OK;
 }
 
 void aceapex_decoder_destroy(aceapex_decoder* d) {
   if (!d) return;
-  for (auto& e : d->ev)
-    if (e) (void)hipEventDestroy(e);
+  ax::plan_destroy(d->plan);
   delete d;
 }
 
@@ -1155,133 +1500,104 @@ int aceapex_decoder_info(const aceapex_decoder* d, aceapex_info* info) {
 
 int aceapex_decoder_workspace(const aceapex_decoder* d, uint64_t* bytes) {
   if (!d || !bytes) return ax::fail(AX_E_ARG, "null argument");
-  *bytes = d->lay.total;
+  *bytes = ax::plan_workspace(d->plan);
   return AX_OK;
 }
 
 int aceapex_decoder_set_timing(aceapex_decoder* d, int enable) {
   if (!d) return ax::fail(AX_E_ARG, "null decoder");
-  if (enable && !d->events_ok) {
-    for (auto& e : d->ev) {
-      hipError_t er = hipEventCreate(&e);
-      if (er != hipSuccess) return hip_fail(er, "hipEventCreate");
-    }
-    d->events_ok = true;
-  }
-  d->timing = enable != 0;
-  return AX_OK;
+  return ax::plan_set_timing(d->plan, enable);
 }
 
 int aceapex_decoder_set_option(aceapex_decoder* d, int option, int64_t value) {
   if (!d) return ax::fail(AX_E_ARG, "null decoder");
-  switch (option) {
-    case AX_OPT_BULK_ROUNDS:
-      if (value < 1 || value > 250) return ax::fail(AX_E_ARG, "bulk rounds must be in [1, 250]");
-      d->bulk_rounds = int(value);
-      return AX_OK;
-    case AX_OPT_TAIL_CHUNKS:
-      if (value < 1 || value > 64) return ax::fail(AX_E_ARG, "tail chunks must be in [1, 64]");
-      d->tail_chunks = int(value);
-      return AX_OK;
-    case AX_OPT_FILL_ROUNDS:
-    case AX_OPT_FILL_TAIL:
-      if (value < 0 || value > 1) return ax::fail(AX_E_ARG, "fill mode must be 0 or 1");
-      (option == AX_OPT_FILL_ROUNDS ? d->fill_round : d->fill_tail) = int(value);
-      return AX_OK;
-    default:
-      return ax::fail(AX_E_ARG, "unknown option");
-  }
+  return ax::plan_set_option(d->plan, option, value);
 }
 
 int aceapex_decoder_stage_ms(aceapex_decoder* d, float* ans, float* parse, float* copy) {
   if (!d || !ans || !parse || !copy) return ax::fail(AX_E_ARG, "null argument");
-  if (!d->events_ok) return ax::fail(AX_E_ARG, "timing not enabled");
-  hipError_t e = hipEventSynchronize(d->ev[3]);
-  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-  (void)hipEventElapsedTime(ans, d->ev[0], d->ev[1]);
-  (void)hipEventElapsedTime(parse, d->ev[1], d->ev[2]);
-  (void)hipEventElapsedTime(copy, d->ev[2], d->ev[3]);
-  return AX_OK;
+  return ax::plan_stage_ms(d->plan, ans, parse, copy);
 }
 
 int aceapex_decode_all(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, void* d_work, uint64_t work_len,
                        int copy_mode, void* stream) {
   if (!d || (!d_out && d->info.n_bytes) || !d_work) return ax::fail(AX_E_ARG, "null argument");
   if (out_cap < d->info.n_bytes) return ax::fail(AX_E_CAPACITY, "output smaller than the decoded size");
-  if (work_len < d->lay.total) return ax::fail(AX_E_CAPACITY, "workspace too small");
-  if ((reinterpret_cast<uintptr_t>(d_work) & 255) || (reinterpret_cast<uintptr_t>(d_out) & 15))
-    return ax::fail(AX_E_ARG, "workspace must be 256-byte and output 16-byte aligned");
-  if (copy_mode != AX_COPY_PERIODIC && copy_mode != AX_COPY_SERIAL) return ax::fail(AX_E_ARG, "bad copy mode");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  uint8_t* w = static_cast<uint8_t*>(d_work);
-  const Layout& L = d->lay;
-  DevStatus* st = reinterpret_cast<DevStatus*>(w + L.status);
-  const aceapex_info& I = d->info;
-  const uint64_t nb = I.n_blocks, B = I.block_size;
-  const bool timed = d->timing && d->events_ok;
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, st);
-  for (uint64_t b0 = 0; b0 < nb; b0 += d->window_blocks) {
-    const uint32_t items = uint32_t(std::min<uint64_t>(nb - b0, d->window_blocks));
-    const bool first = b0 == 0, last = b0 + items == nb;
-    hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st);
-    AnsArgs aa{d->d_arc, I.header_bytes, b0, items, uint32_t(B), w + L.lit, w + L.cmd, w + L.off, w + L.len,
-               d->off_cap, d->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
-    if (timed && first) (void)hipEventRecord(d->ev[0], s);
-    hipLaunchKernelGGL(k_ans, dim3(4 * items), dim3(64), 0, s, aa);
-    if (timed && first) (void)hipEventRecord(d->ev[1], s);
-    const uint64_t t0 = d->mpre[b0], t1 = d->mpre[b0 + items];
-    ParseArgs pa{d->d_arc, I.n_bytes, b0, items, uint32_t(B), I.min_match, w + L.lit, w + L.cmd, w + L.off,
-                 w + L.len, d->off_cap, d->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), t0, t1 - t0,
-                 reinterpret_cast<uint64_t*>(w + L.tok), w + L.done, d_out, st};
-    hipLaunchKernelGGL(k_parse, dim3(items), dim3(kParseThreads), 0, s, pa);
-    if (timed && first) (void)hipEventRecord(d->ev[2], s);
-    const uint32_t ntok = uint32_t(t1 - t0);
-    if (ntok) {
-      uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(w + L.list0), reinterpret_cast<uint32_t*>(w + L.list1)};
-      uint32_t* counts = reinterpret_cast<uint32_t*>(w + L.counts);
-      auto cset = [&](int r) { return counts + (r % 3) * kSub * kCounterStride; };
-      const uint64_t* mpre_dev = reinterpret_cast<const uint64_t*>(d->d_arc + 64) + (nb + 1);
-      hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(256), 0, s, counts, uint32_t(3 * kSub * kCounterStride));
-      CopyArgs ca{reinterpret_cast<const uint64_t*>(w + L.tok), mpre_dev, t0, uint32_t(B), ntok, b0 * B, d_out,
-                  reinterpret_cast<uint32_t*>(w + L.cov), w + L.done, nullptr, lists[0], nullptr,
-                  cset(0), cset(1), uint32_t(L.sub_cap), reinterpret_cast<uint32_t*>(w + L.llist), &st->long_count,
-                  0, st, (ntok + 63) / 64, 1ull << 22,
-                  copy_mode == AX_COPY_SERIAL, d->fill_round, d->fill_tail, uint32_t(d->tail_chunks)};
-      const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
-      hipLaunchKernelGGL(k_round<true>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
-      hipLaunchKernelGGL(k_long, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
-      for (int r = 1; r < d->bulk_rounds; ++r) {
-        ca.round = uint32_t(r);
-        ca.list_in = lists[(r - 1) & 1];
-        ca.list_out = lists[r & 1];
-        ca.cnt_in = cset(r - 1);
-        ca.cnt_out = cset(r);
-        ca.cnt_clear = cset(r + 1);
-        // later rounds see the previous round's leftovers only: a smaller grid
-        hipLaunchKernelGGL(k_round<false>, dim3(std::min<uint32_t>(grid, 512)), dim3(kCopyThreads), 0, s, ca);
-      }
-      ca.round = uint32_t(d->bulk_rounds);
-      const uint64_t waves = (ntok + 64ull * d->tail_chunks - 1) / (64ull * d->tail_chunks);
-      const uint32_t tgrid = uint32_t(std::min<uint64_t>((waves + 3) / 4, uint64_t(d->copy_grid)));
-      hipLaunchKernelGGL(k_tail, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);
-    }
-    if (timed && last) (void)hipEventRecord(d->ev[3], s);
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "kernel launch");
-  return AX_OK;
+  ax::plan_set_out(d->plan, 0, d_out);
+  return ax::plan_run(d->plan, d_work, work_len, copy_mode, reinterpret_cast<hipStream_t>(stream));
 }
 
 int aceapex_decoder_status(aceapex_decoder* d, void* d_work, void* stream, int32_t* dev_err, uint64_t* bad_block) {
   if (!d || !d_work || !dev_err || !bad_block) return ax::fail(AX_E_ARG, "null argument");
-  DevStatus hs;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = hipMemcpyAsync(&hs, static_cast<uint8_t*>(d_work) + d->lay.status, sizeof(hs), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "status read");
-  *dev_err = hs.err;
-  *bad_block = hs.bad_block;
+  return ax::workspace_status(d_work, reinterpret_cast<hipStream_t>(stream), dev_err, bad_block);
+}
+
+int aceapex_workspace_status(void* d_work, void* stream, int32_t* dev_err, uint64_t* bad_block) {
+  if (!d_work || !dev_err || !bad_block) return ax::fail(AX_E_ARG, "null argument");
+  return ax::workspace_status(d_work, reinterpret_cast<hipStream_t>(stream), dev_err, bad_block);
+}
+
+// ------------------------------------------------------------------ batch --
+
+struct aceapex_batch {
+  ax::Plan* plan = nullptr;
+};
+
+int aceapex_batch_create(const aceapex_job* jobs, uint32_t n, aceapex_batch** out) {
+  if (!out || (!jobs && n)) return ax::fail(AX_E_ARG, "null argument");
+  *out = nullptr;
+  std::vector<ax::JobSpec> specs;
+  try {
+    specs.reserve(n);
+    for (uint32_t i = 0; i < n; ++i) {
+      if (!jobs[i].dec) return ax::fail(AX_E_ARG, "job without a decoder");
+      if (jobs[i].out_cap < jobs[i].dec->info.n_bytes) return ax::fail(AX_E_CAPACITY, "job output too small");
+      specs.push_back(ax::JobSpec{jobs[i].dec, jobs[i].d_out, {}});
+    }
+  } catch (const std::bad_alloc&) {
+    return ax::fail(AX_E_NOMEM, "batch jobs");
+  }
+  aceapex_batch* bt = new (std::nothrow) aceapex_batch;
+  if (!bt) return ax::fail(AX_E_NOMEM, "batch handle");
+  int rc = ax::plan_create(specs, &bt->plan);
+  if (rc) {
+    delete bt;
+    return rc;
+  }
+  *out = bt;
   return AX_OK;
+}
+
+void aceapex_batch_destroy(aceapex_batch* bt) {
+  if (!bt) return;
+  ax::plan_destroy(bt->plan);
+  delete bt;
+}
+
+int aceapex_batch_workspace(const aceapex_batch* bt, uint64_t* bytes) {
+  if (!bt || !bytes) return ax::fail(AX_E_ARG, "null argument");
+  *bytes = ax::plan_workspace(bt->plan);
+  return AX_OK;
+}
+
+int aceapex_batch_set_option(aceapex_batch* bt, int option, int64_t value) {
+  if (!bt) return ax::fail(AX_E_ARG, "null batch");
+  return ax::plan_set_option(bt->plan, option, value);
+}
+
+int aceapex_batch_set_timing(aceapex_batch* bt, int enable) {
+  if (!bt) return ax::fail(AX_E_ARG, "null batch");
+  return ax::plan_set_timing(bt->plan, enable);
+}
+
+int aceapex_batch_stage_ms(aceapex_batch* bt, float* ans, float* parse, float* copy) {
+  if (!bt || !ans || !parse || !copy) return ax::fail(AX_E_ARG, "null argument");
+  return ax::plan_stage_ms(bt->plan, ans, parse, copy);
+}
+
+int aceapex_decode_batch(aceapex_batch* bt, void* d_work, uint64_t work_len, int copy_mode, void* stream) {
+  if (!bt) return ax::fail(AX_E_ARG, "null batch");
+  return ax::plan_run(bt->plan, d_work, work_len, copy_mode, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -1,0 +1,58 @@
+// Internal interface between the decoder engine (decoder.hip) and the host
+// pieces built on it (range decode and serving).  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "aceapex.h"
+
+namespace ax {
+
+struct Plan;
+
+// Schedule knobs of a plan; none changes a decoded byte.
+struct PlanOptions {
+  int bulk_rounds = 4;  // level-synchronous match-layer rounds before the persistent launch
+  int fill_round = 1;   // round 0: segmented fill
+  int fill_tail = 0;    // later rounds and persistent launch: lane/wave fill
+  int tail_chunks = 1;  // 64-token chunks per persistent-launch ticket
+  int graph = 0;        // replay the launch sequence from a captured hipGraph
+};
+
+// One archive to decode: all blocks (blocks empty) or the listed blocks
+// (ascending).  Its bytes land in out at their absolute positions.
+struct JobSpec {
+  const aceapex_decoder* dec;
+  uint8_t* out;
+  std::vector<uint64_t> blocks;
+};
+
+constexpr uint32_t kWindowBlocks = 32768;
+constexpr uint64_t kWindowTokens = uint64_t(1) << 24;
+
+int plan_create(const std::vector<JobSpec>& jobs, Plan** out);
+void plan_destroy(Plan* p);
+uint64_t plan_workspace(const Plan* p);
+uint64_t plan_tokens(const Plan* p);
+uint64_t plan_blocks(const Plan* p);
+int plan_set_out(Plan* p, size_t job, uint8_t* out);
+int plan_set_option(Plan* p, int option, int64_t value);
+int plan_get_option(const Plan* p, int option, int64_t* value);
+int plan_set_timing(Plan* p, int enable);
+int plan_stage_ms(Plan* p, float* ans, float* parse, float* copy);
+int plan_run(Plan* p, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s);
+int workspace_status(void* d_work, hipStream_t s, int32_t* dev_err, uint64_t* bad_block);
+
+}  // namespace ax
+
+// The decoder handle: a host copy of the archive's header and index, the
+// device archive, and the plan of a whole-archive decode.
+struct aceapex_decoder {
+  aceapex_info info{};
+  std::vector<uint64_t> offs, mpre;  // payload offsets and cumulative match counts per block
+  const uint8_t* d_arc = nullptr;
+  uint64_t arc_len = 0;
+  ax::Plan* plan = nullptr;
+};
