@@ -205,6 +205,53 @@ int aceapex_batch_stage_ms(aceapex_batch* batch, float* ans_ms, float* parse_ms,
  * aceapex_workspace_status. */
 int aceapex_decode_batch(aceapex_batch* batch, void* d_work, uint64_t work_len, int copy_mode, void* stream);
 
+/* -------------------------------------------------------- random access --- */
+
+/* Build the decoder's token index (every match: src, dst, len) on the host,
+ * by a device entropy + parse pass over the archive (random-access section:
+ * the index is what makes a range's source closure computable without
+ * decoding the archive).  d_full: a device buffer of info.n_bytes (receives
+ * literal bytes as a side effect); d_work: the decode_all workspace.
+ * Synchronous; host memory 16 bytes per match. */
+int aceapex_decoder_build_index(aceapex_decoder* dec, uint8_t* d_full, void* d_work, uint64_t work_len,
+                                void* stream);
+
+/* Byte-precise source closure of n ranges: the ascending union of the blocks
+ * holding any byte the ranges need (their own bytes and, transitively, the
+ * bytes their matches copy).  blocks may be NULL to only count; *n_tokens
+ * (nullable) receives their match count.  Needs the token index.  Closures
+ * run on `threads` host threads (0 = all). */
+int aceapex_closure_blocks(aceapex_decoder* dec, uint32_t n, const uint64_t* h_offs, const uint64_t* h_lens,
+                           uint64_t* h_blocks, uint64_t cap, uint64_t* n_blocks, uint64_t* n_tokens,
+                           uint32_t threads);
+
+/* A reusable range-decode plan with capacity limits (blocks and matches of
+ * one call's closure, at most 32768 blocks and 2^24 matches); its workspace
+ * size depends only on the limits. */
+typedef struct aceapex_range_plan aceapex_range_plan;
+int aceapex_range_plan_create(aceapex_decoder* dec, uint64_t max_blocks, uint64_t max_tokens,
+                              aceapex_range_plan** out);
+void aceapex_range_plan_destroy(aceapex_range_plan* rp);
+int aceapex_range_plan_workspace(const aceapex_range_plan* rp, uint64_t* bytes);
+/* Blocks and matches of the last call's closure. */
+int aceapex_range_plan_last(const aceapex_range_plan* rp, uint64_t* blocks, uint64_t* tokens);
+
+/* Decode n byte ranges [h_offs[i], h_offs[i] + h_lens[i]) of the archive:
+ * their union closure is decoded into d_full (a device buffer of
+ * info.n_bytes, at absolute positions; bytes outside the closure are left
+ * as they were) and range i is then copied to d_outs[i] (a host array of
+ * device pointers, h_lens[i] bytes each).  The closure is computed on the
+ * host before anything is enqueued; the decode and the copies are
+ * asynchronous on `stream`.  AX_E_CAPACITY when the closure exceeds the
+ * plan's limits, AX_E_RANGE for a range outside the archive.  Calls sharing
+ * d_full or d_work must be ordered (same stream). */
+int aceapex_decode_ranges(aceapex_range_plan* rp, uint32_t n, const uint64_t* h_offs, const uint64_t* h_lens,
+                          uint8_t* const* h_d_outs, uint8_t* d_full, void* d_work, uint64_t work_len, int copy_mode,
+                          void* stream);
+/* One range (aceapex_decode_ranges with n = 1, periodic copy). */
+int aceapex_decode_range(aceapex_range_plan* rp, uint64_t off, uint64_t len, uint8_t* d_out, uint8_t* d_full,
+                         void* d_work, uint64_t work_len, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,8 @@ EXPORTS = [
     "aceapex_decoder_set_timing", "aceapex_decoder_status", "aceapex_decoder_set_option",
     "aceapex_workspace_status", "aceapex_batch_create", "aceapex_batch_destroy", "aceapex_batch_workspace",
     "aceapex_batch_set_option", "aceapex_batch_set_timing", "aceapex_batch_stage_ms", "aceapex_decode_batch",
+    "aceapex_decoder_build_index", "aceapex_closure_blocks", "aceapex_range_plan_create", "aceapex_range_plan_destroy",
+    "aceapex_range_plan_workspace", "aceapex_range_plan_last", "aceapex_decode_ranges", "aceapex_decode_range",
 ]
 OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH = 1, 2, 3, 4, 5
 
@@ -97,6 +99,16 @@ def _load():
     L.aceapex_batch_set_timing.argtypes = [vp, ctypes.c_int]
     L.aceapex_batch_stage_ms.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float)]
     L.aceapex_decode_batch.argtypes = [vp, vp, u64, ctypes.c_int, vp]
+    u64p = P(u64)
+    L.aceapex_decoder_build_index.argtypes = [vp, vp, vp, u64, vp]
+    L.aceapex_closure_blocks.argtypes = [vp, ctypes.c_uint32, u64p, u64p, u64p, u64, u64p, u64p, ctypes.c_uint32]
+    L.aceapex_range_plan_create.argtypes = [vp, u64, u64, P(vp)]
+    L.aceapex_range_plan_destroy.argtypes = [vp]
+    L.aceapex_range_plan_destroy.restype = None
+    L.aceapex_range_plan_workspace.argtypes = [vp, u64p]
+    L.aceapex_range_plan_last.argtypes = [vp, u64p, u64p]
+    L.aceapex_decode_ranges.argtypes = [vp, ctypes.c_uint32, u64p, u64p, P(vp), vp, vp, u64, ctypes.c_int, vp]
+    L.aceapex_decode_range.argtypes = [vp, u64, u64, vp, vp, vp, u64, vp]
     _lib = L
     return L
 
@@ -221,6 +233,28 @@ class Decoder:
                                               ctypes.byref(err), ctypes.byref(bad)), "decoder_status")
         return err.value, bad.value
 
+    def build_index(self, full, stream=None, work=None):
+        """Token index for range closures (device parse pass; synchronous)."""
+        w = self.workspace() if work is None else work
+        _check(_load().aceapex_decoder_build_index(self._h, ctypes.c_void_p(full.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                                   w.numel(), _stream_ptr(stream)), "build_index")
+
+    def closure_blocks(self, offs, lens, threads=0, want_blocks=True):
+        """Union source closure of ranges: (ascending block array, match count)."""
+        o = np.ascontiguousarray(offs, dtype=np.uint64)
+        ln = np.ascontiguousarray(lens, dtype=np.uint64)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        nb, nt = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_load().aceapex_closure_blocks(self._h, o.size, o.ctypes.data_as(u64p), ln.ctypes.data_as(u64p), None, 0,
+                                              ctypes.byref(nb), ctypes.byref(nt), threads), "closure_blocks")
+        if not want_blocks:
+            return None, nt.value, nb.value
+        blocks = np.zeros(max(1, nb.value), np.uint64)
+        _check(_load().aceapex_closure_blocks(self._h, o.size, o.ctypes.data_as(u64p), ln.ctypes.data_as(u64p),
+                                              blocks.ctypes.data_as(u64p), blocks.size, ctypes.byref(nb),
+                                              ctypes.byref(nt), threads), "closure_blocks")
+        return blocks[: nb.value], nt.value, nb.value
+
     def stage_ms(self):
         a, p, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
         _check(_load().aceapex_decoder_stage_ms(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(c)),
@@ -290,3 +324,40 @@ class Batch:
 
     def status(self, stream=None, work=None):
         return workspace_status(self.workspace() if work is None else work, stream)
+
+
+class RangePlan:
+    """Reusable range decode (aceapex_decode_ranges) for one decoder."""
+
+    def __init__(self, decoder, max_blocks=4096, max_tokens=1 << 20):
+        self.decoder = decoder
+        self._h = ctypes.c_void_p()
+        _check(_load().aceapex_range_plan_create(decoder._h, int(max_blocks), int(max_tokens), ctypes.byref(self._h)),
+               "range_plan_create")
+        ws = ctypes.c_uint64()
+        _check(_load().aceapex_range_plan_workspace(self._h, ctypes.byref(ws)), "range_plan_workspace")
+        self.workspace_bytes = ws.value
+        self.max_blocks, self.max_tokens = int(max_blocks), int(max_tokens)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.aceapex_range_plan_destroy(self._h)
+            self._h = None
+
+    def last(self):
+        b, t = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_load().aceapex_range_plan_last(self._h, ctypes.byref(b), ctypes.byref(t)), "range_plan_last")
+        return b.value, t.value
+
+    def decode(self, offs, lens, outs, full, work, copy_mode=COPY_PERIODIC, stream=None):
+        """Enqueue the decode of ranges; outs: CUDA uint8 tensors (len each).
+        Raises AceapexError(AX_E_CAPACITY) when the closure exceeds the limits."""
+        n = len(offs)
+        o = np.ascontiguousarray(offs, dtype=np.uint64)
+        ln = np.ascontiguousarray(lens, dtype=np.uint64)
+        ptrs = (ctypes.c_void_p * max(1, n))(*[t.data_ptr() for t in outs])
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        rc = _load().aceapex_decode_ranges(self._h, n, o.ctypes.data_as(u64p), ln.ctypes.data_as(u64p), ptrs,
+                                           ctypes.c_void_p(full.data_ptr()), ctypes.c_void_p(work.data_ptr()),
+                                           work.numel(), int(copy_mode), _stream_ptr(stream))
+        _check(rc, "decode_ranges")

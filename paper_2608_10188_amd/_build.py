@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libaceapex.so")
-SOURCES = ["csrc/decoder.hip", "csrc/encoder.cpp", "csrc/ax_common.cpp"]
+SOURCES = ["csrc/decoder.hip", "csrc/range.hip", "csrc/encoder.cpp", "csrc/ax_common.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1073,6 +1073,7 @@ struct Layout {
 struct Plan {
   std::vector<JobDev> jobs;
   std::vector<WinBlock> wbl;
+  std::vector<uint64_t> gtok;  // per window block: its first token's index in its archive
   struct Win {
     uint64_t at;       // first WinBlock
     uint32_t items;    // blocks
@@ -1085,6 +1086,9 @@ struct Plan {
   JobDev* d_jobs = nullptr;
   WinBlock* d_wbl = nullptr;
   JobDev* h_pinned = nullptr;  // staging for refreshing output pointers
+  uint8_t* h_stage = nullptr;  // staging for plan_reset uploads
+  size_t dev_cap = 0, stage_cap = 0, pinned_cap = 0;
+  hipEvent_t staged = nullptr;  // the last upload from h_stage / h_pinned
   std::vector<uint8_t*> dev_out;  // output pointers as last uploaded
   Layout lay{};
   PlanOptions opt{};
@@ -1102,8 +1106,13 @@ struct Plan {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    if (staged) {
+      (void)hipEventSynchronize(staged);
+      (void)hipEventDestroy(staged);
+    }
     if (d_mem) (void)hipFree(d_mem);
     if (h_pinned) (void)hipHostFree(h_pinned);
+    if (h_stage) (void)hipHostFree(h_stage);
   }
 };
 
@@ -1137,12 +1146,15 @@ static int hip_fail(hipError_t e, const char* what) {
   return fail(AX_E_HIP, hipGetErrorString(e));
 }
 
-int plan_create(const std::vector<JobSpec>& specs, Plan** out) {
-  *out = nullptr;
-  Plan* P = new (std::nothrow) Plan;
-  if (!P) return fail(AX_E_NOMEM, "plan");
+// Host tables of a plan: jobs, window blocks, windows, maxima.
+static int build_tables(Plan* P, const std::vector<JobSpec>& specs) {
   try {
-    P->jobs.resize(specs.size());
+    P->jobs.assign(specs.size(), JobDev{});
+    P->wbl.clear();
+    P->gtok.clear();
+    P->wins.clear();
+    P->max_items = P->max_tok = P->slot_b = P->off_cap = P->len_cap = 0;
+    P->out_bytes = P->n_tokens = 0;
     uint64_t gblocks = 0;
     for (size_t j = 0; j < specs.size(); ++j) {
       const aceapex_decoder* d = specs[j].dec;
@@ -1162,13 +1174,13 @@ int plan_create(const std::vector<JobSpec>& specs, Plan** out) {
       gblocks += specs[j].blocks.empty() ? I.n_blocks : specs[j].blocks.size();
     }
     P->wbl.reserve(gblocks);
+    P->gtok.reserve(gblocks);
     // windows: consecutive (job, block) items, at most kWindowBlocks blocks
     // and kWindowTokens tokens each
     Plan::Win cur{0, 0, 0};
     auto close = [&]() {
       if (!cur.items) return;
-      // per-job extents inside the window
-      for (uint64_t i = cur.at; i < cur.at + cur.items;) {
+      for (uint64_t i = cur.at; i < cur.at + cur.items;) {  // per-job extents inside the window
         uint64_t k = i;
         while (k < cur.at + cur.items && P->wbl[k].job == P->wbl[i].job) ++k;
         for (uint64_t m = i; m < k; ++m) {
@@ -1188,29 +1200,76 @@ int plan_create(const std::vector<JobSpec>& specs, Plan** out) {
       const uint64_t nb = specs[j].blocks.empty() ? d->info.n_blocks : specs[j].blocks.size();
       for (uint64_t i = 0; i < nb; ++i) {
         const uint64_t b = specs[j].blocks.empty() ? i : specs[j].blocks[i];
+        if (b >= d->info.n_blocks) return fail(AX_E_RANGE, "block outside the archive");
         const uint64_t nt = d->mpre[b + 1] - d->mpre[b];
         if (cur.items == kWindowBlocks || uint64_t(cur.tok) + nt > kWindowTokens) close();
         P->wbl.push_back(WinBlock{b, uint32_t(j), cur.tok, 0, 0});
+        P->gtok.push_back(d->mpre[b]);
         cur.items++;
         cur.tok += uint32_t(nt);
       }
     }
     close();
   } catch (const std::bad_alloc&) {
-    delete P;
     return fail(AX_E_NOMEM, "plan tables");
   }
+  P->lay = make_layout(*P);
+  return AX_OK;
+}
+
+static size_t table_bytes(const Plan* P, size_t* wbl_at) {
   const size_t jb = sizeof(JobDev) * std::max<size_t>(1, P->jobs.size());
-  const size_t wb = sizeof(WinBlock) * std::max<size_t>(1, P->wbl.size());
-  hipError_t e = hipMalloc(&P->d_mem, align256(jb) + wb);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&P->h_pinned), jb);
-  if (e != hipSuccess) {
-    delete P;
-    return hip_fail(e, "plan memory");
+  *wbl_at = align256(jb);
+  return *wbl_at + sizeof(WinBlock) * std::max<size_t>(1, P->wbl.size());
+}
+
+// Device tables big enough for the current host tables (grown when needed).
+static int ensure_device(Plan* P) {
+  size_t wbl_at;
+  const size_t need = table_bytes(P, &wbl_at);
+  if (need > P->dev_cap) {
+    if (P->d_mem) (void)hipFree(P->d_mem), P->d_mem = nullptr;
+    const size_t cap = std::max(need, 2 * P->dev_cap);
+    hipError_t e = hipMalloc(&P->d_mem, cap);
+    if (e != hipSuccess) return hip_fail(e, "plan memory");
+    P->dev_cap = cap;
+  }
+  const size_t jb = sizeof(JobDev) * std::max<size_t>(1, P->jobs.size());
+  if (jb > P->pinned_cap) {
+    if (P->h_pinned) (void)hipHostFree(P->h_pinned), P->h_pinned = nullptr;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&P->h_pinned), jb);
+    if (e != hipSuccess) return hip_fail(e, "plan staging");
+    P->pinned_cap = jb;
   }
   P->d_jobs = static_cast<JobDev*>(P->d_mem);
-  P->d_wbl = reinterpret_cast<WinBlock*>(static_cast<uint8_t*>(P->d_mem) + align256(jb));
-  if (!P->jobs.empty()) e = hipMemcpy(P->d_jobs, P->jobs.data(), sizeof(JobDev) * P->jobs.size(), hipMemcpyHostToDevice);
+  P->d_wbl = reinterpret_cast<WinBlock*>(static_cast<uint8_t*>(P->d_mem) + wbl_at);
+  if (!P->staged) {
+    hipError_t e = hipEventCreateWithFlags(&P->staged, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "plan event");
+  }
+  return AX_OK;
+}
+
+static int device_setup(Plan* P) {
+  int dev = 0, cus = 0, occ = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_tail), kCopyThreads, 0);
+  P->copy_grid = std::max(1, cus) * std::max(1, occ);
+  return AX_OK;
+}
+
+int plan_create(const std::vector<JobSpec>& specs, Plan** out) {
+  *out = nullptr;
+  Plan* P = new (std::nothrow) Plan;
+  if (!P) return fail(AX_E_NOMEM, "plan");
+  int rc = build_tables(P, specs);
+  if (!rc) rc = ensure_device(P);
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  hipError_t e = hipMemcpy(P->d_jobs, P->jobs.data(), sizeof(JobDev) * P->jobs.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !P->wbl.empty())
     e = hipMemcpy(P->d_wbl, P->wbl.data(), sizeof(WinBlock) * P->wbl.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -1219,16 +1278,100 @@ int plan_create(const std::vector<JobSpec>& specs, Plan** out) {
   }
   P->dev_out.resize(P->jobs.size());
   for (size_t j = 0; j < P->jobs.size(); ++j) P->dev_out[j] = P->jobs[j].out;
-  P->lay = make_layout(*P);
-  int dev = 0, cus = 0, occ = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_tail), kCopyThreads, 0);
-  P->copy_grid = std::max(1, cus) * std::max(1, occ);
+  device_setup(P);
   *out = P;
   return AX_OK;
 }
 
+int plan_reset(Plan* P, const std::vector<JobSpec>& specs, hipStream_t s) {
+  // staging may still feed the previous upload
+  if (P->staged) (void)hipEventSynchronize(P->staged);
+  int rc = build_tables(P, specs);
+  if (!rc) rc = ensure_device(P);
+  if (rc) return rc;
+  size_t wbl_at;
+  const size_t bytes = table_bytes(P, &wbl_at);
+  if (bytes > P->stage_cap) {
+    if (P->h_stage) (void)hipHostFree(P->h_stage), P->h_stage = nullptr;
+    const size_t cap = std::max(bytes, 2 * P->stage_cap);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&P->h_stage), cap);
+    if (e != hipSuccess) return hip_fail(e, "plan staging");
+    P->stage_cap = cap;
+  }
+  std::memcpy(P->h_stage, P->jobs.data(), sizeof(JobDev) * P->jobs.size());
+  if (!P->wbl.empty()) std::memcpy(P->h_stage + wbl_at, P->wbl.data(), sizeof(WinBlock) * P->wbl.size());
+  hipError_t e = hipMemcpyAsync(P->d_mem, P->h_stage, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(P->staged, s);
+  if (e != hipSuccess) return hip_fail(e, "plan upload");
+  P->dev_out.resize(P->jobs.size());
+  for (size_t j = 0; j < P->jobs.size(); ++j) P->dev_out[j] = P->jobs[j].out;
+  if (P->graph) (void)hipGraphExecDestroy(P->graph), P->graph = nullptr;  // tables changed
+  if (!P->copy_grid || P->copy_grid == 1) device_setup(P);
+  return AX_OK;
+}
+
+uint64_t plan_workspace_for(const aceapex_decoder* d, uint64_t max_blocks, uint64_t max_tokens) {
+  Plan P;
+  P.max_items = uint32_t(max_blocks);
+  P.max_tok = uint32_t(max_tokens);
+  P.slot_b = d->info.block_size;
+  P.off_cap = uint32_t((10 * (d->info.block_size / d->info.min_match + 1) + 15) & ~15u);
+  P.len_cap = 3 * d->info.block_size;
+  return make_layout(P).total;
+}
+
+void plan_copy_options(Plan* dst, const Plan* src) { dst->opt = src->opt; }
+
+int plan_parse_tokens(Plan* P, void* d_work, uint64_t work_len, hipStream_t s, uint64_t* src, uint64_t* dstlen) {
+  if (work_len < P->lay.total) return fail(AX_E_CAPACITY, "workspace too small");
+  uint8_t* w = static_cast<uint8_t*>(d_work);
+  const Layout& L = P->lay;
+  DevStatus* st = reinterpret_cast<DevStatus*>(w + L.status);
+  bool stale = false;
+  for (size_t j = 0; j < P->jobs.size(); ++j) stale |= P->dev_out[j] != P->jobs[j].out;
+  if (stale) {
+    hipError_t e = hipMemcpy(P->d_jobs, P->jobs.data(), sizeof(JobDev) * P->jobs.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "job table update");
+    for (size_t j = 0; j < P->jobs.size(); ++j) P->dev_out[j] = P->jobs[j].out;
+  }
+  std::vector<uint64_t> tk;
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, st);
+  for (const Plan::Win& W : P->wins) {
+    const WinBlock* wbl = P->d_wbl + W.at;
+    hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st);
+    AnsArgs aa{P->d_jobs, wbl, W.items, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
+               P->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
+    hipLaunchKernelGGL(k_ans, dim3(4 * W.items), dim3(64), 0, s, aa);
+    ParseArgs pa{P->d_jobs, wbl, W.items, W.tok, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
+                 P->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), reinterpret_cast<uint64_t*>(w + L.tok),
+                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st};
+    hipLaunchKernelGGL(k_parse, dim3(W.items), dim3(kParseThreads), 0, s, pa);
+    try {
+      tk.resize(2ull * W.tok);
+    } catch (const std::bad_alloc&) {
+      return fail(AX_E_NOMEM, "token staging");
+    }
+    hipError_t e = W.tok ? hipMemcpyAsync(tk.data(), w + L.tok, 16ull * W.tok, hipMemcpyDeviceToHost, s) : hipSuccess;
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "token copy");
+    int32_t err = 0;
+    uint64_t bad = 0;
+    int rc = workspace_status(d_work, s, &err, &bad);
+    if (rc) return rc;
+    if (err) return fail(err, "device status during the index build");
+    // window tokens are the tokens of its blocks in order
+    for (uint32_t i = 0; i < W.items; ++i) {
+      const WinBlock& wb = P->wbl[W.at + i];
+      const uint32_t end = i + 1 < W.items ? P->wbl[W.at + i + 1].tok : W.tok;
+      const uint64_t g0 = P->gtok[W.at + i];
+      for (uint32_t t = wb.tok; t < end; ++t) {
+        src[g0 + (t - wb.tok)] = tk[2ull * t];
+        dstlen[g0 + (t - wb.tok)] = tk[2ull * t + 1];
+      }
+    }
+  }
+  return AX_OK;
+}
 void plan_destroy(Plan* P) { delete P; }
 uint64_t plan_workspace(const Plan* P) { return P->lay.total; }
 uint64_t plan_tokens(const Plan* P) { return P->n_tokens; }
@@ -1368,8 +1511,10 @@ int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_
   bool stale = false;
   for (size_t j = 0; j < P->jobs.size(); ++j) stale |= P->dev_out[j] != P->jobs[j].out;
   if (stale) {
+    if (P->staged) (void)hipEventSynchronize(P->staged);  // h_pinned may feed the previous update
     std::memcpy(P->h_pinned, P->jobs.data(), sizeof(JobDev) * P->jobs.size());
     hipError_t e = hipMemcpyAsync(P->d_jobs, P->h_pinned, sizeof(JobDev) * P->jobs.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && P->staged) e = hipEventRecord(P->staged, s);
     if (e != hipSuccess) return hip_fail(e, "job table update");
     for (size_t j = 0; j < P->jobs.size(); ++j) P->dev_out[j] = P->jobs[j].out;
   }

@@ -33,6 +33,15 @@ constexpr uint32_t kWindowBlocks = 32768;
 constexpr uint64_t kWindowTokens = uint64_t(1) << 24;
 
 int plan_create(const std::vector<JobSpec>& jobs, Plan** out);
+// Rebuild an existing plan for new jobs, reusing its device tables (grown
+// only when too small); the upload is asynchronous on s.
+int plan_reset(Plan* p, const std::vector<JobSpec>& jobs, hipStream_t s);
+// Workspace of a one-window plan of decoder d with these maxima.
+uint64_t plan_workspace_for(const aceapex_decoder* d, uint64_t max_blocks, uint64_t max_tokens);
+void plan_copy_options(Plan* dst, const Plan* src);
+// Entropy + parse only, every window; the match tokens (src; dst | (len-1)
+// << 48) are copied to host arrays in archive order.  Synchronous.
+int plan_parse_tokens(Plan* p, void* d_work, uint64_t work_len, hipStream_t s, uint64_t* src, uint64_t* dstlen);
 void plan_destroy(Plan* p);
 uint64_t plan_workspace(const Plan* p);
 uint64_t plan_tokens(const Plan* p);
@@ -55,4 +64,5 @@ struct aceapex_decoder {
   const uint8_t* d_arc = nullptr;
   uint64_t arc_len = 0;
   ax::Plan* plan = nullptr;
+  std::vector<uint64_t> idx_src, idx_dstlen;  // token index (aceapex_decoder_build_index)
 };

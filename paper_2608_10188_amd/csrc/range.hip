@@ -1,0 +1,298 @@
+// Random access: byte-precise source closure of a range and its decode.
+//
+// A range [off, off+len) needs its own bytes, and for every match that
+// writes one of them the source bytes that match copies (periodic form:
+// byte k of a match comes from src + k mod dist), transitively.  Because
+// offsets are absolute and sources lie below their destinations (Setup), the
+// closure is a finite set of byte intervals, and the blocks it touches are
+// all a decode of the range needs (random-access section: seek into a
+// resident archive).  The token index behind this (the matches of every
+// block) is built once by a device parse of the archive.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <map>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "aceapex.h"
+#include "ax_common.h"
+#include "engine.h"
+
+namespace {
+
+// Merged set of disjoint half-open intervals.
+class IntervalSet {
+ public:
+  // Insert [a, b); append to `added` the parts that were not present.
+  void insert(uint64_t a, uint64_t b, std::vector<std::pair<uint64_t, uint64_t>>& added) {
+    if (a >= b) return;
+    auto it = m_.upper_bound(a);
+    if (it != m_.begin()) {
+      auto p = std::prev(it);
+      if (p->second >= a) it = p;
+    }
+    uint64_t cur = a, lo = a, hi = b;
+    while (it != m_.end() && it->first <= b) {
+      if (it->first > cur) added.emplace_back(cur, it->first);
+      cur = std::max(cur, it->second);
+      lo = std::min(lo, it->first);
+      hi = std::max(hi, it->second);
+      it = m_.erase(it);
+    }
+    if (cur < b) added.emplace_back(cur, b);
+    m_.emplace(lo, hi);
+  }
+  const std::map<uint64_t, uint64_t>& items() const { return m_; }
+
+ private:
+  std::map<uint64_t, uint64_t> m_;
+};
+
+// Closure of one range: needed intervals, from the highest position down.
+void closure_of(const aceapex_decoder* d, uint64_t off, uint64_t len, IntervalSet& need) {
+  const uint64_t B = d->info.block_size;
+  const auto& src = d->idx_src;
+  const auto& dl = d->idx_dstlen;
+  std::vector<std::pair<uint64_t, uint64_t>> work, added;
+  need.insert(off, off + len, work);
+  while (!work.empty()) {
+    const auto iv = work.back();
+    work.pop_back();
+    // matches of the blocks under [a, b)
+    for (uint64_t blk = iv.first / B; blk <= (iv.second - 1) / B; ++blk) {
+      uint64_t lo = d->mpre[blk], hi = d->mpre[blk + 1];
+      // first match ending after a
+      uint64_t x = lo, y = hi;
+      while (x < y) {
+        const uint64_t mid = (x + y) / 2;
+        const uint64_t e = (dl[mid] & ((1ull << 48) - 1)) + (dl[mid] >> 48) + 1;
+        if (e <= iv.first) x = mid + 1; else y = mid;
+      }
+      for (uint64_t t = x; t < hi; ++t) {
+        const uint64_t dst = dl[t] & ((1ull << 48) - 1), n = (dl[t] >> 48) + 1;
+        if (dst >= iv.second) break;
+        const uint64_t k0 = std::max(iv.first, dst) - dst, k1 = std::min(iv.second, dst + n) - dst;
+        const uint64_t dist = dst - src[t];
+        added.clear();
+        if (k1 - k0 >= dist) {
+          need.insert(src[t], src[t] + std::min(n, dist), added);
+        } else {
+          const uint64_t a = k0 % dist, b = a + (k1 - k0);
+          if (b <= dist) need.insert(src[t] + a, src[t] + b, added);
+          else need.insert(src[t] + a, src[t] + dist, added), need.insert(src[t], src[t] + (b - dist), added);
+        }
+        for (auto& p : added) work.push_back(p);
+      }
+    }
+  }
+}
+
+void blocks_of(const IntervalSet& need, uint64_t B, std::vector<uint64_t>& out) {
+  for (const auto& iv : need.items())
+    for (uint64_t b = iv.first / B; b <= (iv.second - 1) / B; ++b)
+      if (out.empty() || out.back() != b) out.push_back(b);
+}
+
+// Closures of many ranges in parallel, merged into one ascending block list.
+int union_closure(const aceapex_decoder* d, uint32_t n, const uint64_t* offs, const uint64_t* lens,
+                  std::vector<uint64_t>& blocks, uint32_t threads) {
+  const uint64_t N = d->info.n_bytes;
+  for (uint32_t i = 0; i < n; ++i)
+    if (offs[i] > N || lens[i] > N - offs[i]) return ax::fail(AX_E_RANGE, "range outside the archive");
+  if (d->idx_dstlen.size() != d->info.n_matches) return ax::fail(AX_E_ARG, "token index not built");
+  const uint32_t T = std::max(1u, std::min(threads ? threads : std::thread::hardware_concurrency(), n ? n : 1));
+  std::vector<std::vector<uint64_t>> part(T);
+  std::atomic<uint32_t> next{0};
+  auto worker = [&](uint32_t w) {
+    for (;;) {
+      const uint32_t i = next.fetch_add(1);
+      if (i >= n) break;
+      if (!lens[i]) continue;
+      IntervalSet need;
+      closure_of(d, offs[i], lens[i], need);
+      blocks_of(need, d->info.block_size, part[w]);
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (uint32_t w = 1; w < T; ++w) pool.emplace_back(worker, w);
+    worker(0);
+    for (auto& t : pool) t.join();
+    blocks.clear();
+    for (auto& p : part) blocks.insert(blocks.end(), p.begin(), p.end());
+    std::sort(blocks.begin(), blocks.end());
+    blocks.erase(std::unique(blocks.begin(), blocks.end()), blocks.end());
+  } catch (const std::bad_alloc&) {
+    return ax::fail(AX_E_NOMEM, "closure");
+  }
+  return AX_OK;
+}
+
+// Copy range bytes from the full-size scratch output to each caller buffer.
+struct GatherDesc {
+  const uint8_t* src;
+  uint8_t* dst;
+  uint64_t len;
+};
+
+__global__ void k_gather(const GatherDesc* desc, uint32_t n) {
+  for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
+    const GatherDesc g = desc[r];
+    for (uint64_t k = threadIdx.x; k < g.len; k += blockDim.x) g.dst[k] = g.src[k];
+  }
+}
+
+}  // namespace
+
+// A reusable range-decode plan: the decoder, capacity limits, and the plan of
+// the current block set.
+struct aceapex_range_plan {
+  aceapex_decoder* dec = nullptr;
+  uint64_t max_blocks = 0, max_tokens = 0;
+  ax::Plan* plan = nullptr;          // rebuilt per call
+  uint64_t workspace = 0;            // for max_blocks / max_tokens
+  GatherDesc* d_desc = nullptr;
+  GatherDesc* h_desc = nullptr;
+  uint32_t desc_cap = 0;
+  hipEvent_t upload_done = nullptr;  // the pinned descriptors may be rewritten after this
+  uint64_t last_blocks = 0, last_tokens = 0;
+  ~aceapex_range_plan() {
+    if (upload_done) {
+      (void)hipEventSynchronize(upload_done);
+      (void)hipEventDestroy(upload_done);
+    }
+    ax::plan_destroy(plan);
+    if (d_desc) (void)hipFree(d_desc);
+    if (h_desc) (void)hipHostFree(h_desc);
+  }
+};
+
+extern "C" {
+
+int aceapex_decoder_build_index(aceapex_decoder* d, uint8_t* d_full, void* d_work, uint64_t work_len, void* stream) {
+  if (!d || !d_full || !d_work) return ax::fail(AX_E_ARG, "null argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  try {
+    d->idx_src.assign(d->info.n_matches, 0);
+    d->idx_dstlen.assign(d->info.n_matches, 0);
+  } catch (const std::bad_alloc&) {
+    return ax::fail(AX_E_NOMEM, "token index");
+  }
+  ax::plan_set_out(d->plan, 0, d_full);
+  return ax::plan_parse_tokens(d->plan, d_work, work_len, s, d->idx_src.data(), d->idx_dstlen.data());
+}
+
+int aceapex_closure_blocks(aceapex_decoder* d, uint32_t n, const uint64_t* offs, const uint64_t* lens,
+                           uint64_t* blocks, uint64_t cap, uint64_t* n_blocks, uint64_t* n_tokens, uint32_t threads) {
+  if (!d || (n && (!offs || !lens)) || !n_blocks) return ax::fail(AX_E_ARG, "null argument");
+  std::vector<uint64_t> bl;
+  int rc = union_closure(d, n, offs, lens, bl, threads);
+  if (rc) return rc;
+  *n_blocks = bl.size();
+  if (n_tokens) {
+    uint64_t t = 0;
+    for (uint64_t b : bl) t += d->mpre[b + 1] - d->mpre[b];
+    *n_tokens = t;
+  }
+  if (blocks) {
+    if (cap < bl.size()) return ax::fail(AX_E_CAPACITY, "block list capacity");
+    std::copy(bl.begin(), bl.end(), blocks);
+  }
+  return AX_OK;
+}
+
+int aceapex_range_plan_create(aceapex_decoder* d, uint64_t max_blocks, uint64_t max_tokens,
+                              aceapex_range_plan** out) {
+  if (!d || !out || !max_blocks) return ax::fail(AX_E_ARG, "null argument");
+  *out = nullptr;
+  if (max_blocks > ax::kWindowBlocks || max_tokens > ax::kWindowTokens)
+    return ax::fail(AX_E_ARG, "range plans hold one window of blocks");
+  aceapex_range_plan* rp = new (std::nothrow) aceapex_range_plan;
+  if (!rp) return ax::fail(AX_E_NOMEM, "range plan");
+  rp->dec = d;
+  rp->max_blocks = max_blocks;
+  rp->max_tokens = max_tokens;
+  rp->workspace = ax::plan_workspace_for(d, max_blocks, max_tokens);
+  if (hipEventCreateWithFlags(&rp->upload_done, hipEventDisableTiming) != hipSuccess) {
+    delete rp;
+    return ax::fail(AX_E_HIP, "event");
+  }
+  *out = rp;
+  return AX_OK;
+}
+
+void aceapex_range_plan_destroy(aceapex_range_plan* rp) { delete rp; }
+
+int aceapex_range_plan_workspace(const aceapex_range_plan* rp, uint64_t* bytes) {
+  if (!rp || !bytes) return ax::fail(AX_E_ARG, "null argument");
+  *bytes = rp->workspace;
+  return AX_OK;
+}
+
+int aceapex_range_plan_last(const aceapex_range_plan* rp, uint64_t* blocks, uint64_t* tokens) {
+  if (!rp || !blocks || !tokens) return ax::fail(AX_E_ARG, "null argument");
+  *blocks = rp->last_blocks;
+  *tokens = rp->last_tokens;
+  return AX_OK;
+}
+
+int aceapex_decode_ranges(aceapex_range_plan* rp, uint32_t n, const uint64_t* offs, const uint64_t* lens,
+                          uint8_t* const* d_outs, uint8_t* d_full, void* d_work, uint64_t work_len, int copy_mode,
+                          void* stream) {
+  if (!rp || (n && (!offs || !lens || !d_outs)) || !d_full || !d_work) return ax::fail(AX_E_ARG, "null argument");
+  if (work_len < rp->workspace) return ax::fail(AX_E_CAPACITY, "workspace too small");
+  aceapex_decoder* d = rp->dec;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<uint64_t> bl;
+  int rc = union_closure(d, n, offs, lens, bl, 0);
+  if (rc) return rc;
+  uint64_t tok = 0;
+  for (uint64_t b : bl) tok += d->mpre[b + 1] - d->mpre[b];
+  if (bl.size() > rp->max_blocks || tok > rp->max_tokens)
+    return ax::fail(AX_E_CAPACITY, "closure larger than the plan's capacity");
+  rp->last_blocks = bl.size();
+  rp->last_tokens = tok;
+  // the previous call's uploads must be through before staging is rewritten
+  (void)hipEventSynchronize(rp->upload_done);
+  if (!bl.empty()) {
+    if (!rp->plan) {
+      rc = ax::plan_create({ax::JobSpec{d, d_full, std::move(bl)}}, &rp->plan);
+    } else {
+      rc = ax::plan_reset(rp->plan, {ax::JobSpec{d, d_full, std::move(bl)}}, s);
+    }
+    if (rc) return rc;
+    ax::plan_copy_options(rp->plan, d->plan);
+    rc = ax::plan_run(rp->plan, d_work, work_len, copy_mode, s);
+    if (rc) return rc;
+  }
+  if (n) {
+    if (n > rp->desc_cap) {
+      if (rp->d_desc) (void)hipFree(rp->d_desc), rp->d_desc = nullptr;
+      if (rp->h_desc) (void)hipHostFree(rp->h_desc), rp->h_desc = nullptr;
+      rp->desc_cap = std::max<uint32_t>(n, 2 * rp->desc_cap);
+      hipError_t e = hipMalloc(reinterpret_cast<void**>(&rp->d_desc), sizeof(GatherDesc) * rp->desc_cap);
+      if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&rp->h_desc), sizeof(GatherDesc) * rp->desc_cap);
+      if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
+    }
+    for (uint32_t i = 0; i < n; ++i) rp->h_desc[i] = GatherDesc{d_full + offs[i], d_outs[i], lens[i]};
+    hipError_t e = hipMemcpyAsync(rp->d_desc, rp->h_desc, sizeof(GatherDesc) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
+    hipLaunchKernelGGL(k_gather, dim3(std::min<uint32_t>(n, 4096)), dim3(256), 0, s, rp->d_desc, n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
+  }
+  (void)hipEventRecord(rp->upload_done, s);
+  return AX_OK;
+}
+
+int aceapex_decode_range(aceapex_range_plan* rp, uint64_t off, uint64_t len, uint8_t* d_out, uint8_t* d_full,
+                         void* d_work, uint64_t work_len, void* stream) {
+  uint8_t* outs[1] = {d_out};
+  return aceapex_decode_ranges(rp, 1, &off, &len, outs, d_full, d_work, work_len, AX_COPY_PERIODIC, stream);
+}
+
+}  // extern "C"

@@ -32,6 +32,27 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(ax.EXPORTS) | set(names)
 
 
+def _declared_arity():
+    with open(os.path.join(ROOT, "include", "aceapex.h")) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(aceapex_\w+)\s*\(([^;{]*?)\)\s*;", text, flags=re.S):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    """Every ctypes prototype has exactly the parameters the header declares."""
+    lib = ax.lib()
+    arity = _declared_arity()
+    assert len(arity) >= 20
+    for name, n in arity.items():
+        fn = getattr(lib, name)
+        assert fn.argtypes is not None, name
+        assert len(fn.argtypes) == n, (name, len(fn.argtypes), n)
+
+
 def test_strerror_and_params():
     lib = ax.lib()
     assert lib.aceapex_strerror(ax.AX_E_CORRUPT) == b"corrupt archive"
