@@ -65,14 +65,16 @@ const char* aceapex_last_error(void);
  *   hash_bits              hash-chain head table size (22)
  *   chain_depth            candidates walked per position (32)
  *   rans_min_syms_per_lane S of the rANS lane rule (128)
- *   off_cost               an explicit-offset match must be at least
- *                          min_match + off_cost * LEB128 bytes of its offset (2)
+ *   off_cost_q             an explicit-offset match must be at least
+ *                          min_match + ceil(off_cost_q * (LEB128 bytes of its
+ *                          offset) / 4) long: the offset's cost in quarter
+ *                          bytes per LEB128 byte (6)
  *   window_log             0 = candidates anywhere behind; else only within
  *                          2^window_log bytes behind the position (0)
  *   threads                encoder threads, 0 = hardware concurrency (0) */
 typedef struct {
   uint32_t block_size, min_match, no_rep, depth_cap, hash_bits, chain_depth;
-  uint32_t rans_min_syms_per_lane, off_cost, window_log, threads;
+  uint32_t rans_min_syms_per_lane, off_cost_q, window_log, threads;
 } aceapex_encode_params;
 
 /* Encoder statistics.  n_src_bytes = sum over matches of min(len, dist): the

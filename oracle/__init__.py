@@ -17,7 +17,7 @@ OK, E_ARG, E_CORRUPT, E_NOMEM, E_CHECKSUM = 0, -1, -2, -3, -4
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "block_size", "min_match", "no_rep", "depth_cap", "hash_bits", "chain_depth",
-        "rans_min_syms_per_lane", "off_cost", "window_log")]
+        "rans_min_syms_per_lane", "off_cost_q", "window_log")]
 
 
 class Stats(ctypes.Structure):

@@ -63,7 +63,7 @@ void axo_params_default(axo_params* p) {
   p->hash_bits = 22;
   p->chain_depth = 32;
   p->rans_min_syms_per_lane = 128;
-  p->off_cost = 2;
+  p->off_cost_q = 6;
   p->window_log = 0;
 }
 
@@ -399,6 +399,7 @@ static int check_params(const axo_params* p) {
   if (p->min_match < 1 || p->min_match > 255) return AXO_E_ARG;
   if (p->hash_bits < 10 || p->hash_bits > 26) return AXO_E_ARG;
   if (p->window_log > 40) return AXO_E_ARG;
+  if (p->off_cost_q > 4096) return AXO_E_ARG;
   return AXO_OK;
 }
 
@@ -472,10 +473,10 @@ static int encode_pass(const uint8_t* in, uint64_t n, const axo_params* p, const
         }
       }
       /* An explicit match pays for its absolute offset: it must be at least
-       * min_match + off_cost bytes per LEB128 byte of src.  A repeat match
-       * sends no offset and needs only min_match. */
+       * min_match + ceil(off_cost_q * (LEB128 bytes of src) / 4).  A
+       * repeat match sends no offset and needs only min_match. */
       uint8_t lb[10];
-      uint64_t need_abs = mm + (uint64_t)p->off_cost * axo_leb_put(src_abs, lb);
+      uint64_t need_abs = mm + ((uint64_t)p->off_cost_q * axo_leb_put(src_abs, lb) + 3) / 4;
       int take_rep = lrep >= mm && lrep >= labs;
       int take_abs = !take_rep && labs >= need_abs;
       if (!take_rep && !take_abs) { pos++; continue; }

@@ -42,8 +42,9 @@ typedef struct {
   uint32_t hash_bits;              /* 10..26 */
   uint32_t chain_depth;            /* candidates walked per position */
   uint32_t rans_min_syms_per_lane; /* S in the lane rule */
-  uint32_t off_cost;               /* an explicit-offset match must be at least
-                                      min_match + off_cost * (LEB128 bytes of src) long */
+  uint32_t off_cost_q;             /* an explicit-offset match must be at least
+                                      min_match + ceil(off_cost_q * (LEB128 bytes
+                                      of src) / 4) long: quarter bytes per byte */
   uint32_t window_log;             /* 0: candidates anywhere behind; else only
                                       those at most 2^window_log bytes behind */
 } axo_params;

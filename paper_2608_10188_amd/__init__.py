@@ -42,7 +42,7 @@ class AceapexError(RuntimeError):
 class EncodeParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "block_size", "min_match", "no_rep", "depth_cap", "hash_bits", "chain_depth",
-        "rans_min_syms_per_lane", "off_cost", "window_log", "threads")]
+        "rans_min_syms_per_lane", "off_cost_q", "window_log", "threads")]
 
 
 class EncodeStats(ctypes.Structure):

@@ -5,8 +5,8 @@
 // iterated forced-literal depth cap (depth section).  The bytes are a pure
 // function of (input, parameters): threads only split independent blocks.
 //
-// Structure: the hash chains of a segment are built first in one sequential
-// pass (every position enters its chain whatever the parse does), after which
+// Structure: the hash chains of a segment are built first, independent of the
+// parse (every position enters its chain whatever the parse does), after which
 // every block of the segment can be encoded on any thread, because a block's
 // decisions depend only on the chains, the input and its own history.
 #include <algorithm>
@@ -57,19 +57,58 @@ struct Params {
 };
 
 // Chains for positions [r0, r1): link[q - r0] = previous position with the
-// same hash (relative to r0), or kNil.
+// same hash (relative to r0), or kNil.  Built in parallel: each part of the
+// range chains its own positions and records, per hash, its first and last
+// position; a second pass over disjoint hash ranges links every part's first
+// occurrence to the last occurrence in the parts before it.  The links equal
+// those of one sequential pass.
 struct Chains {
   uint64_t r0 = 0;
   std::vector<uint32_t> link;
-  void build(const uint8_t* in, uint64_t n, uint64_t a, uint64_t b, uint32_t bits) {
+  void build(const uint8_t* in, uint64_t n, uint64_t a, uint64_t b, uint32_t bits, unsigned threads) {
     r0 = a;
     link.assign(b - a, kNil);
-    std::vector<uint32_t> head(size_t(1) << bits, kNil);
-    for (uint64_t q = a; q < b && q + 4 <= n; ++q) {
-      uint32_t h = hash_at(in + q, bits);
-      link[q - a] = head[h];
-      head[h] = uint32_t(q - a);
+    const uint64_t end = std::min<uint64_t>(b, n >= 4 ? n - 3 : 0);  // positions with 4 bytes left
+    if (end <= a) return;
+    const size_t H = size_t(1) << bits;
+    const uint64_t span = end - a;
+    const unsigned P = unsigned(std::max<uint64_t>(1, std::min<uint64_t>(threads, span >> 22)));
+    std::vector<std::vector<uint32_t>> first(P), last(P);
+    auto chain_part = [&](unsigned p) {
+      const uint64_t lo = a + span * p / P, hi = a + span * (p + 1) / P;
+      last[p].assign(H, kNil);
+      if (p) first[p].assign(H, kNil);
+      uint32_t* L = last[p].data();
+      uint32_t* F = p ? first[p].data() : nullptr;
+      for (uint64_t q = lo; q < hi; ++q) {
+        const uint32_t h = hash_at(in + q, bits), r = uint32_t(q - a);
+        link[r] = L[h];
+        if (F && L[h] == kNil) F[h] = r;
+        L[h] = r;
+      }
+    };
+    auto stitch = [&](unsigned t) {
+      const size_t h0 = H * t / P, h1 = H * (t + 1) / P;
+      for (size_t h = h0; h < h1; ++h) {
+        uint32_t g = last[0][h];
+        for (unsigned p = 1; p < P; ++p) {
+          if (first[p][h] != kNil) link[first[p][h]] = g;
+          if (last[p][h] != kNil) g = last[p][h];
+        }
+      }
+    };
+    if (P == 1) {
+      chain_part(0);
+      return;
     }
+    std::vector<std::thread> pool;
+    for (unsigned p = 1; p < P; ++p) pool.emplace_back(chain_part, p);
+    chain_part(0);
+    for (auto& th : pool) th.join();
+    pool.clear();
+    for (unsigned t = 1; t < P; ++t) pool.emplace_back(stitch, t);
+    stitch(0);
+    for (auto& th : pool) th.join();
   }
 };
 
@@ -117,7 +156,7 @@ void encode_block(const uint8_t* in, uint64_t n, const Params& P, const Chains& 
         c = ch.link[cand - ch.r0];
       }
     }
-    const uint64_t abs_need = mm + uint64_t(p.off_cost) * ax::leb_size(abs_src);
+    const uint64_t abs_need = mm + (uint64_t(p.off_cost_q) * ax::leb_size(abs_src) + 3) / 4;
     if (best_rep >= mm && best_rep >= best_abs) {
       flush_literals(pos);
       bs.add_rep(rep_idx, best_rep, mm);
@@ -178,7 +217,7 @@ int encode_pass(const uint8_t* in, uint64_t n, const Params& P, const uint8_t* f
     uint64_t s1 = std::min(n, s0 + seg);
     uint64_t r0 = (P.window && s0 > P.window) ? s0 - P.window : 0;
     if (s1 - r0 >= kNil) return AX_E_UNSUPPORTED;
-    ch.build(in, n, r0, s1, p.hash_bits);
+    ch.build(in, n, r0, s1, p.hash_bits, T);
     const uint64_t b0 = s0 / B, b1 = (s1 + B - 1) / B;
     std::atomic<uint64_t> next{b0};
     auto worker = [&]() {
@@ -248,7 +287,7 @@ void aceapex_encode_params_default(aceapex_encode_params* p) {
   p->hash_bits = 22;
   p->chain_depth = 32;
   p->rans_min_syms_per_lane = 128;
-  p->off_cost = 2;
+  p->off_cost_q = 6;
   p->window_log = 0;
   p->threads = 0;
 }
@@ -260,6 +299,7 @@ static int check_params(const aceapex_encode_params* p) {
   if (p->min_match < 1 || p->min_match > 255) return ax::fail(AX_E_ARG, "min_match must be in [1, 255]");
   if (p->hash_bits < 10 || p->hash_bits > 26) return ax::fail(AX_E_ARG, "hash_bits must be in [10, 26]");
   if (p->window_log > 40) return ax::fail(AX_E_ARG, "window_log must be <= 40");
+  if (p->off_cost_q > 4096) return ax::fail(AX_E_ARG, "off_cost_q must be <= 4096");
   return AX_OK;
 }
 

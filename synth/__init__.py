@@ -24,6 +24,7 @@ def _load():
         u64p = ctypes.POINTER(ctypes.c_uint64)
         lib.axs_dna.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64]
         lib.axs_text.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64]
+        lib.axs_dna_segmented.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]
         lib.axs_batch_plan.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u64p, u8p]
         lib.axs_trace.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                   ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, u64p, u64p, u64p]
@@ -46,6 +47,14 @@ def dna(n, seed):
     out = np.empty(int(n), dtype=np.uint8)
     if _load().axs_dna(_u8(out), int(n), int(seed)) != 0:
         raise MemoryError("axs_dna")
+    return out
+
+
+def dna_segmented(n, seed, seg=256 << 20, threads=16):
+    """Large synthetic DNA: independent segments of `seg` bytes, in parallel."""
+    out = np.empty(int(n), dtype=np.uint8)
+    if _load().axs_dna_segmented(_u8(out), int(n), int(seed), int(seg), int(threads)) != 0:
+        raise MemoryError("axs_dna_segmented")
     return out
 
 

@@ -57,7 +57,7 @@ def test_strerror_and_params():
     lib = ax.lib()
     assert lib.aceapex_strerror(ax.AX_E_CORRUPT) == b"corrupt archive"
     p = ax.encode_params()
-    assert (p.block_size, p.min_match, p.chain_depth, p.off_cost) == (16384, 4, 32, 2)
+    assert (p.block_size, p.min_match, p.chain_depth, p.off_cost_q) == (16384, 4, 32, 6)
 
 
 @pytest.mark.parametrize("kind", ["dna", "text"])
@@ -69,6 +69,15 @@ def test_library_encoder_matches_oracle_bytes(kind, kw):
     for threads in (1, 3):
         got = ax.encode(x, threads=threads, **kw)
         assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("kw", [{}, {"window_log": 20}])
+def test_library_encoder_parallel_chains_match_oracle(kw):
+    """Inputs above 4 Mi positions per thread build their hash chains in
+    parallel parts stitched together; the archive must not change."""
+    x = synth.dna(13 << 20, 33)
+    want, _ = oracle.encode(x, **kw)
+    assert np.array_equal(ax.encode(x, threads=3, **kw), want)
 
 
 @pytest.mark.parametrize("x", [b"", b"z", b"abc" * 7000, bytes(range(256)) * 100])

@@ -304,7 +304,7 @@ def test_encoding_is_deterministic():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("cap", [2, 4, 8])
+@pytest.mark.parametrize("cap", [2, 8, 16])
 def test_depth_cap_invariants(cap):
     """Depth section: the cap bounds every depth, changes no decoded byte, and
     the blocks whose streams differ from the uncapped encoding are exactly the
@@ -325,7 +325,8 @@ def test_depth_cap_invariants(cap):
     forced_blocks = set(np.unique(np.nonzero(forced)[0] // 4096).tolist())
     assert len(forced_blocks) > 0 and int(forced.sum()) == sc.n_forced_bytes
     assert differ == forced_blocks
-    assert len(differ) < nb
+    if cap >= 8:  # uncapped depth here is 24: a loose cap leaves blocks untouched
+        assert len(differ) < nb
 
 
 # ------------------------------------------------- depth, levels, closure --
