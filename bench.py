@@ -1,6 +1,6 @@
 """Benchmark: device-resident full decode of the 254 MB synthetic DNA archive.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dna254|text200|dna4]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dna254|text200|dna4|batch|serve]
                 [--copy periodic|serial] [--no-rep] [--no-cpu-baseline]
 
 One step = one aceapex_decode_all of the whole archive (rANS of the four
@@ -8,7 +8,13 @@ streams of every block, command parse with literal placement, match copy with
 periodic fills scheduled by source readiness), inputs resident in HBM.
 Prints one JSON line.  The archive is generated and encoded on the host first
 (outside the timed region); the decode is checked byte for byte against the
-original before timing.
+original before timing.  After the timed steps, 16 KiB reads of the same
+archive are served one at a time (closed loop) for their p50/p99 latency.
+
+--workload batch: thousands of archives in one plan against the plain
+per-archive loop.  --workload serve: a synthetic DNA archive held compressed
+on the device (32 GiB by default) served to open-loop Poisson request traces
+with continuous batching, against one-request-at-a-time service.
 """
 import argparse
 import concurrent.futures as cf
@@ -38,13 +44,23 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="dna254", choices=sorted(WORKLOADS) + ["batch"])
+    ap.add_argument("--workload", default="dna254", choices=sorted(WORKLOADS) + ["batch", "serve"])
     ap.add_argument("--batch-count", type=int, default=4096, help="archives in the batched workload")
     ap.add_argument("--autotune", action="store_true", help="batched workload: tune knobs per size class")
     ap.add_argument("--copy", default="periodic", choices=["periodic", "serial"])
     ap.add_argument("--no-rep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--threads", type=int, default=0, help="encoder threads (0 = all)")
+    ap.add_argument("--threads", type=int, default=16, help="encoder threads (0 = all)")
+    ap.add_argument("--reads", type=int, default=1000, help="closed-loop 16 KiB reads after the timed steps")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration under a profiler)")
+    ap.add_argument("--serve-bytes", type=int, default=32 << 30, help="serving archive size")
+    ap.add_argument("--rates", default="2000,5000,20000,50000,200000", help="serving arrival rates, req/s")
+    ap.add_argument("--requests", type=int, default=10000, help="requests per serving trace point")
+    ap.add_argument("--sizes", default="16k,mixed", help="serving request sizes: 16k and/or mixed (16 KiB-1 MiB)")
+    ap.add_argument("--slots", type=int, default=3, help="serving slots (concurrent batches)")
+    ap.add_argument("--max-blocks", type=int, default=32768, help="serving admission limit: closure blocks per batch")
+    ap.add_argument("--max-tokens", type=int, default=1 << 23, help="serving admission limit: matches per batch")
     ap.add_argument("--bulk-rounds", type=int, default=0, help="level-synchronous copy rounds (0 = library default)")
     ap.add_argument("--tail-chunks", type=int, default=0, help="chunks per persistent-launch ticket (0 = default)")
     ap.add_argument("--fill", default="", help="fill modes 'R,T' for rounds and tail (0 lane/wave, 1 segmented)")
@@ -68,6 +84,133 @@ def cpu_baseline(arc, n_bytes):
     t = float(np.median(times))
     return {"value": n_bytes / t / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"whole archive ({n_bytes} B), median of 3 single-threaded oracle decodes, {t:.2f} s each"}
+
+
+def _pcts(ns):
+    ns = np.asarray(ns, dtype=np.float64)
+    return round(float(np.percentile(ns, 50)) / 1e3, 1), round(float(np.percentile(ns, 99)) / 1e3, 1)
+
+
+def read_latency(ax, dec, x, full, count, size, seed, max_blocks, max_tokens):
+    """Closed loop: `count` reads of `size` bytes at trace-generated offsets
+    (80% Zipf-local, 20% uniform), each issued alone and waited for.  Latency
+    runs from the host call (closure, plan upload, kernels) to the device
+    event after the copy-out; every read is checked against the input."""
+    import torch
+
+    import synth
+
+    dev = full.device
+    _, offs, lens = synth.trace(count, seed, x.size, 16384, 1000.0, size, size)
+    plan = ax.RangePlan(dec, max_blocks, max_tokens)
+    work = torch.empty(max(256, plan.workspace_bytes), dtype=torch.uint8, device=dev)
+    outs = torch.empty((count, size), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    lat, blocks = [], []
+    for i in range(count):
+        torch.cuda.synchronize()
+        t = time.perf_counter_ns()
+        plan.decode([int(offs[i])], [size], [outs[i]], full, work, stream=stream)
+        end = torch.cuda.Event()
+        end.record(stream)
+        end.synchronize()
+        lat.append(time.perf_counter_ns() - t)
+        blocks.append(plan.last()[0])
+    got = outs.cpu().numpy()
+    bad = sum(not np.array_equal(got[i], x[int(offs[i]): int(offs[i]) + size]) for i in range(count))
+    p50, p99 = _pcts(lat)
+    return {"p50_us": p50, "p99_us": p99, "reads": count, "bytes": size, "mismatches": int(bad),
+            "closure_blocks_mean": round(float(np.mean(blocks)), 1), "mode": "closed loop, one read at a time"}
+
+
+# ------------------------------------------------- served workload (config 5)
+#
+# A DNA archive held compressed in HBM; Poisson request traces at several
+# arrival rates, served by the continuous-batching loop, against the same
+# trace served one request at a time through the same range decoder.
+
+def run_serve(args, log):
+    import torch
+
+    import synth
+    import paper_2608_10188_amd as ax
+    from paper_2608_10188_amd.serve import Server
+
+    n = int(args.serve_bytes)
+    marks = set()
+
+    def gen_progress(done, total):
+        g = done * 8 // total
+        if g not in marks:
+            marks.add(g)
+            log(f"generated {done >> 20} of {total >> 20} MiB")
+
+    t0 = time.time()
+    x = synth.dna_segmented(n, 5, threads=16, progress=gen_progress)
+    log(f"generated {n} B in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    arc, st = ax.encode(x, stats=True, window_log=30 if n >= (1 << 32) else 0, threads=args.threads,
+                        progress=lambda d, t: log(f"encoded {d >> 20} of {t >> 20} MiB in {time.time() - t0:.0f}s"))
+    log(f"encoded to {arc.size} B (ratio {n / arc.size:.3f}) in {time.time() - t0:.1f}s; "
+        f"{st.n_matches} matches over {st.n_blocks} blocks")
+    dev = torch.device("cuda:0")
+    d_arc = torch.from_numpy(arc).to(dev)
+    t0 = time.time()
+    srv = Server(arc, d_arc, slots=args.slots, max_blocks=args.max_blocks, max_tokens=args.max_tokens)
+    log(f"server ready in {time.time() - t0:.1f}s (token index built on the device)")
+    unloaded = read_latency(ax, srv.dec, x, srv.slots[0]["full"], args.reads, 16384, 54, args.max_blocks,
+                            args.max_tokens)
+    log(f"unloaded 16 KiB reads: p50 {unloaded['p50_us']} us, p99 {unloaded['p99_us']} us")
+
+    rates = [float(r) for r in args.rates.split(",") if r]
+    points, count = [], int(args.requests)
+    skip = count // 20  # the first 5% of each trace warm the loop up
+    for mode in [m for m in args.sizes.split(",") if m]:
+        lmin, lmax = (16384, 16384) if mode == "16k" else (16384, 1 << 20)
+        for k, rate in enumerate(rates):
+            arr, offs, lens = synth.trace(count, 55 + k, n, 16384, rate, lmin, lmax)
+            buf = torch.empty(int(lens.sum()), dtype=torch.uint8, device=dev)
+            outs = list(torch.split(buf, [int(v) for v in lens]))
+            r = srv.run(arr, offs, lens, outs)
+            got = buf.cpu().numpy()
+            at, bad = 0, 0
+            for i in range(count):
+                o, ln = int(offs[i]), int(lens[i])
+                bad += not np.array_equal(got[at: at + ln], x[o: o + ln])
+                at += ln
+            req_bytes = float(lens.sum())
+            p50, p99 = _pcts(r["latency_ns"][skip:])
+            h50, h99 = _pcts(r["host_latency_ns"][skip:])
+            pt = {"sizes": mode, "rate": rate, "p50_us": p50, "p99_us": p99, "host_p50_us": h50, "host_p99_us": h99,
+                  "served_req_s": round(count / (r["wall_ns"] / 1e9), 1),
+                  "requested_gbs": round(req_bytes / r["wall_ns"], 3), "batches": r["batches"],
+                  "batch_size_mean": round(r["batch_size_mean"], 2),
+                  "closure_blocks_mean": round(r["closure_blocks_mean"], 1),
+                  "decoded_gbs": round(r["closure_blocks_mean"] * r["batches"] * int(srv.dec.info.block_size)
+                                       / r["wall_ns"], 3),
+                  "mismatches": int(bad)}
+            if mode == "16k":
+                b = srv.run(arr, offs, lens, outs, max_batch=1, slots=1)
+                b50, b99 = _pcts(b["latency_ns"][skip:])
+                pt["one_at_a_time"] = {"p50_us": b50, "p99_us": b99,
+                                       "served_req_s": round(count / (b["wall_ns"] / 1e9), 1),
+                                       "requested_gbs": round(req_bytes / b["wall_ns"], 3)}
+            del buf, outs, got
+            log(json.dumps(pt))
+            points.append(pt)
+    best = max(points, key=lambda p: p["requested_gbs"]) if points else None
+    res = {
+        "metric": "served range reads: p50/p99 us per 16 KB read and aggregate requested GB/s",
+        "value": best["requested_gbs"] if best else None, "unit": "GB/s", "n_gpus": 1,
+        "steps": count, "warmup": skip, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"synthetic DNA {n} B held compressed ({arc.size} B), Poisson range reads",
+                   "n_bytes": n, "archive_bytes": int(arc.size), "blocks": int(st.n_blocks),
+                   "matches": int(st.n_matches), "slots": args.slots, "max_blocks": args.max_blocks,
+                   "max_tokens": args.max_tokens, "requests_per_point": count},
+        "unloaded_16k": unloaded, "points": points,
+    }
+    print(json.dumps(res), flush=True)
 
 
 # ------------------------------------------------- batched workload (config 4)
@@ -192,6 +335,9 @@ def main():
     if args.workload == "batch":
         run_batch(args, log)
         return
+    if args.workload == "serve":
+        run_serve(args, log)
+        return
     import torch
     import xxhash
 
@@ -223,6 +369,14 @@ def main():
         dec.set_option(ax.OPT_FILL_ROUNDS, fr)
         dec.set_option(ax.OPT_FILL_TAIL, ft)
     stream = torch.cuda.current_stream()
+    if args.calib_copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE under a
+        # counter profiler give the scale factor for the decode's counters
+        a = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # correctness first (poisoned output), outside the timed region
     out.fill_(0xCC)
@@ -296,6 +450,11 @@ def main():
         "wall_s": round(wall, 3),
         "roofline": roofline,
     }
+    if args.reads:
+        t0 = time.time()
+        dec.build_index(out, work=work)
+        res["read_16k"] = read_latency(ax, dec, x, out, args.reads, 16384, 54, 32768, 1 << 23)
+        log(f"16 KiB reads: {res['read_16k']} ({time.time() - t0:.1f}s)")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(arc, n)
     print(json.dumps(res), flush=True)

@@ -71,10 +71,17 @@ const char* aceapex_last_error(void);
  *                          bytes per LEB128 byte (6)
  *   window_log             0 = candidates anywhere behind; else only within
  *                          2^window_log bytes behind the position (0)
- *   threads                encoder threads, 0 = hardware concurrency (0) */
+ *   threads                encoder threads, 0 = hardware concurrency (0)
+ *   progress, progress_user  optional callback, called on the calling thread
+ *                          after each encoded segment (1 GiB with a window,
+ *                          else the whole input) with the input bytes done
+ *                          and the total; NULL = none (NULL) */
+typedef void (*aceapex_progress_fn)(void* user, uint64_t bytes_done, uint64_t bytes_total);
 typedef struct {
   uint32_t block_size, min_match, no_rep, depth_cap, hash_bits, chain_depth;
   uint32_t rans_min_syms_per_lane, off_cost_q, window_log, threads;
+  aceapex_progress_fn progress;
+  void* progress_user;
 } aceapex_encode_params;
 
 /* Encoder statistics.  n_src_bytes = sum over matches of min(len, dist): the

@@ -39,10 +39,14 @@ class AceapexError(RuntimeError):
         self.code = code
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64)
+
+
 class EncodeParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "block_size", "min_match", "no_rep", "depth_cap", "hash_bits", "chain_depth",
-        "rans_min_syms_per_lane", "off_cost_q", "window_log", "threads")]
+        "rans_min_syms_per_lane", "off_cost_q", "window_log", "threads")] + [
+        ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p)]
 
 
 class EncodeStats(ctypes.Structure):
@@ -134,11 +138,15 @@ def encode_params(**kw):
     return p
 
 
-def encode(data, stats=False, **kw):
-    """Host encode (aceapex_encode).  Returns the archive as a uint8 array."""
+def encode(data, stats=False, progress=None, **kw):
+    """Host encode (aceapex_encode).  Returns the archive as a uint8 array.
+    progress(bytes_done, bytes_total), if given, runs after each segment."""
     a = np.ascontiguousarray(np.frombuffer(data, np.uint8) if isinstance(data, (bytes, bytearray)) else data,
                              dtype=np.uint8)
     p = encode_params(**kw)
+    cb = PROGRESS_FN(lambda _u, done, total: progress(done, total)) if progress else None
+    if cb:
+        p.progress = cb
     bound = ctypes.c_uint64()
     _check(_load().aceapex_encode_bound(a.size, ctypes.byref(p), ctypes.byref(bound)), "encode_bound")
     out = np.empty(bound.value, np.uint8)

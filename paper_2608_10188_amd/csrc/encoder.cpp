@@ -243,6 +243,7 @@ int encode_pass(const uint8_t* in, uint64_t n, const Params& P, const uint8_t* f
     worker();
     for (auto& th : pool) th.join();
     if (err) return err;
+    if (p.progress) p.progress(p.progress_user, s1, n);
   }
   E.n_commands = tot_cmds, E.n_rep = tot_rep, E.n_mbytes = tot_mb, E.n_lit = tot_lit;
   E.n_src = tot_src, E.n_off = tot_off, E.n_len = tot_len;
@@ -290,6 +291,8 @@ void aceapex_encode_params_default(aceapex_encode_params* p) {
   p->off_cost_q = 6;
   p->window_log = 0;
   p->threads = 0;
+  p->progress = nullptr;
+  p->progress_user = nullptr;
 }
 
 static int check_params(const aceapex_encode_params* p) {

@@ -45,16 +45,17 @@ class Server:
         s["plan"].decode([int(offs[i]) for i in ids], [int(lens[i]) for i in ids], [outs[i] for i in ids], s["full"],
                          s["work"], COPY_PERIODIC, stream=s["stream"])
 
-    def run(self, arrivals_ns, offs, lens, outs, realtime=True, max_batch=None):
+    def run(self, arrivals_ns, offs, lens, outs, realtime=True, max_batch=None, slots=None):
         """Serve every request; outs[i] receives range i (a CUDA uint8 tensor
         of lens[i] bytes).  Returns a dict with per-request latency (ns,
-        device timeline), host-observed latency (ns) and batch statistics."""
+        device timeline), host-observed latency (ns) and batch statistics.
+        max_batch=1 with slots=1 serves one request at a time, in order."""
         import torch
 
         n = len(offs)
         max_batch = max_batch or self.max_batch
         arrivals = np.asarray(arrivals_ns, dtype=np.int64)
-        free = collections.deque(range(len(self.slots)))
+        free = collections.deque(range(min(len(self.slots), slots or len(self.slots))))
         inflight = {}
         queue = collections.deque()
         done_ev = [None] * n
@@ -104,7 +105,11 @@ class Server:
             if not progressed and completed < n:
                 time.sleep(20e-6)
         torch.cuda.synchronize()
-        dev_done = np.array([origin.elapsed_time(done_ev[i]) * 1e6 for i in range(n)], dtype=np.float64)
+        ev_ms = {}
+        for ev in done_ev:
+            if id(ev) not in ev_ms:
+                ev_ms[id(ev)] = origin.elapsed_time(ev)
+        dev_done = np.array([ev_ms[id(done_ev[i])] * 1e6 for i in range(n)], dtype=np.float64)
         if not realtime:
             arrivals = np.zeros(n, np.int64)
         return {

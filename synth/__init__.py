@@ -24,7 +24,6 @@ def _load():
         u64p = ctypes.POINTER(ctypes.c_uint64)
         lib.axs_dna.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64]
         lib.axs_text.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64]
-        lib.axs_dna_segmented.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]
         lib.axs_batch_plan.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u64p, u8p]
         lib.axs_trace.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                   ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, u64p, u64p, u64p]
@@ -50,11 +49,31 @@ def dna(n, seed):
     return out
 
 
-def dna_segmented(n, seed, seg=256 << 20, threads=16):
-    """Large synthetic DNA: independent segments of `seg` bytes, in parallel."""
-    out = np.empty(int(n), dtype=np.uint8)
-    if _load().axs_dna_segmented(_u8(out), int(n), int(seed), int(seg), int(threads)) != 0:
-        raise MemoryError("axs_dna_segmented")
+def dna_segmented(n, seed, seg=256 << 20, threads=16, progress=None):
+    """Multi-GiB synthetic DNA: consecutive segments of `seg` bytes, segment i
+    an independent dna() stream seeded seed + i * 0x9E3779B97F4A7C15 (mod
+    2^64), so planted copies source within their segment and a single
+    segment equals dna(n, seed).  Segments are generated on `threads` threads;
+    progress(bytes_done, n), if given, runs as segments finish."""
+    import concurrent.futures as cf
+
+    n = int(n)
+    out = np.empty(n, dtype=np.uint8)
+    lib = _load()
+
+    def one(i):
+        a = i * seg
+        part = out[a: min(n, a + seg)]
+        if lib.axs_dna(_u8(part), part.size, (int(seed) + i * 0x9E3779B97F4A7C15) & (2**64 - 1)) != 0:
+            raise MemoryError("axs_dna")
+        return part.size
+
+    done = 0
+    with cf.ThreadPoolExecutor(max_workers=max(1, int(threads))) as pool:
+        for size in cf.as_completed([pool.submit(one, i) for i in range((n + seg - 1) // seg)]):
+            done += size.result()
+            if progress:
+                progress(done, n)
     return out
 
 

@@ -10,7 +10,6 @@
 #include "axsynth.h"
 
 #include <math.h>
-#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -134,50 +133,6 @@ int axs_dna(uint8_t* out, uint64_t n, uint64_t seed) {
     for (uint64_t k = 0; k < l && pos < n; k++, pos++) out[pos] = 'N';
   }
   return 0;
-}
-
-typedef struct {
-  uint8_t* out;
-  uint64_t n, seed, seg, nseg;
-  uint64_t* next;
-  pthread_mutex_t* mu;
-  int rc;
-} segjob_t;
-
-static void* seg_worker(void* arg) {
-  segjob_t* j = (segjob_t*)arg;
-  for (;;) {
-    pthread_mutex_lock(j->mu);
-    uint64_t i = (*j->next)++;
-    pthread_mutex_unlock(j->mu);
-    if (i >= j->nseg) break;
-    uint64_t a = i * j->seg, len = j->n - a < j->seg ? j->n - a : j->seg;
-    if (axs_dna(j->out + a, len, j->seed + i * 0x9E3779B97F4A7C15ULL)) j->rc = -1;
-  }
-  return NULL;
-}
-
-int axs_dna_segmented(uint8_t* out, uint64_t n, uint64_t seed, uint64_t seg, uint32_t threads) {
-  if (seg == 0) return -1;
-  uint64_t nseg = (n + seg - 1) / seg, next = 0;
-  if (threads < 1) threads = 1;
-  if (threads > 256) threads = 256;
-  pthread_mutex_t mu = PTHREAD_MUTEX_INITIALIZER;
-  pthread_t th[256];
-  segjob_t job[256];
-  uint32_t started = 0;
-  for (uint32_t t = 0; t < threads; t++) {
-    job[t] = (segjob_t){out, n, seed, seg, nseg, &next, &mu, 0};
-    if (pthread_create(&th[t], NULL, seg_worker, &job[t]) == 0) started++;
-    else break;
-  }
-  if (!started) seg_worker(&job[0]);
-  int rc = 0;
-  for (uint32_t t = 0; t < started; t++) {
-    pthread_join(th[t], NULL);
-    rc |= job[t].rc;
-  }
-  return rc;
 }
 
 /* ----------------------------------------------------------------- text --- */

@@ -24,12 +24,6 @@ extern "C" {
 /* Fill out[0..n) with synthetic DNA for `seed`. Returns 0, or -1 on OOM. */
 int axs_dna(uint8_t* out, uint64_t n, uint64_t seed);
 
-/* Large-archive form: out[0..n) as consecutive segments of seg bytes, each
- * an independent axs_dna stream (segment i seeded seed + i * 0x9E3779B97F4A7C15,
- * so one segment equals axs_dna(n, seed)); planted copies source within
- * their segment.  Segments are generated on `threads` threads. */
-int axs_dna_segmented(uint8_t* out, uint64_t n, uint64_t seed, uint64_t seg, uint32_t threads);
-
 /* Fill out[0..n) with synthetic English-like text for `seed`. 0 / -1 on OOM. */
 int axs_text(uint8_t* out, uint64_t n, uint64_t seed);
 
