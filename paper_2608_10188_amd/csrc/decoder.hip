@@ -19,11 +19,13 @@
 //            once by binary search; a token is ready when those are done.
 //            k_round runs level-synchronous rounds (the dependency levels of
 //            the paper's wavefront decoder) with plain cached accesses, the
-//            kernel boundary being the only synchronisation; k_tail then
-//            finishes the deep remainder in one persistent launch, waves
-//            taking 64-token chunks in output order from a ticket counter and
-//            publishing through agent-coherent stores, so a dependency hop
-//            costs a memory round trip rather than an L2 writeback.
+//            kernel boundary being the only synchronisation.  The last round
+//            marks its leftovers in a bitmap, which k_pcount / k_pscatter
+//            compact into an ascending list; k_tail then finishes that deep
+//            remainder in one persistent launch, waves taking 64-token chunks
+//            of the list from a ticket counter and publishing through
+//            agent-coherent stores, so a dependency hop costs a memory round
+//            trip rather than an L2 writeback.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +38,17 @@
 #include "engine.h"
 
 namespace {
+
+// Device pointers that kernels load from memory (job tables) or select at run
+// time lose their address space; accesses through generic pointers become
+// flat instructions, which also count against the LDS wait counter.  Kernels
+// convert them to global pointers explicitly.
+#define AX_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ inline AX_GLOBAL T* gp(T* p) {
+  return (AX_GLOBAL T*)p;
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t kMaxB = 16384;           // largest block the device path decodes
 constexpr uint32_t kParseThreads = 256;
@@ -54,7 +67,8 @@ struct DevStatus {
   unsigned long long bad_block;
   uint32_t ticket;
   uint32_t long_count;
-  uint32_t pad1[58];
+  uint32_t n_pending;  // tokens left for the persistent finish
+  uint32_t pad1[57];
 };
 static_assert(sizeof(DevStatus) == 256, "status block is 256 bytes");
 
@@ -127,6 +141,7 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
   __shared__ uint32_t fctab[256];     // f | cum << 16, indexed by symbol
   __shared__ uint16_t cumtab[257];    // cum of the k-th present symbol, sentinel 4096
   __shared__ uint8_t symlist[256];    // k-th present symbol
+  __shared__ __attribute__((aligned(16))) uint8_t obuf[16 * 64];  // 16 steps of output, flushed as 16-byte stores
 
   const uint32_t item = blockIdx.x % a.n_items;
   const uint32_t stream = blockIdx.x / a.n_items;  // 0 LIT, 1 LEN, 2 OFF, 3 CMD
@@ -137,7 +152,7 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
   uint8_t* const outs[4] = {a.lit + uint64_t(item) * a.slot_b, a.len + uint64_t(item) * a.len_cap,
                             a.off + uint64_t(item) * a.off_cap, a.cmd + uint64_t(item) * a.slot_b};
   const uint32_t caps[4] = {J.B, job_len_cap(J), job_off_cap(J), J.B};
-  uint8_t* out = outs[stream];
+  AX_GLOBAL uint8_t* const out = gp(outs[stream]);
   const uint32_t cap = caps[stream];
   uint32_t* nsym = a.nsym + 4 * item + stream;
 
@@ -165,13 +180,13 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
     }
     const uint32_t words = (n + 3) / 4;
     for (uint32_t w = lane; w < words; w += 64)
-      reinterpret_cast<uint32_t*>(out)[w] = reinterpret_cast<const uint32_t*>(rec + 8)[w];
+      reinterpret_cast<AX_GLOBAL uint32_t*>(out)[w] = gp(reinterpret_cast<const uint32_t*>(rec + 8))[w];
     if (lane == 0) *nsym = n;
     return;
   }
   if (mode == 1) {  // constant
     const uint32_t v = pa * 0x01010101u, words = (n + 3) / 4;
-    for (uint32_t w = lane; w < words; w += 64) reinterpret_cast<uint32_t*>(out)[w] = v;
+    for (uint32_t w = lane; w < words; w += 64) reinterpret_cast<AX_GLOBAL uint32_t*>(out)[w] = v;
     if (lane == 0) *nsym = n;
     return;
   }
@@ -247,7 +262,7 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
   }
   __syncthreads();
   // --- decode: lane j owns symbols j, j+K, ...
-  const uint16_t* words = reinterpret_cast<const uint16_t*>(rec + words_at);
+  const AX_GLOBAL uint16_t* words = gp(reinterpret_cast<const uint16_t*>(rec + words_at));
   uint32_t x = lane < K ? ld32(rec + states_at + 4 * lane) : ax::kRansLow;
   bad = x < ax::kRansLow;
   auto fetch = [&](uint32_t i) -> uint32_t { return i < nw ? uint32_t(words[i]) : 0u; };
@@ -270,7 +285,7 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
     const uint32_t w = q < 64 ? va : vb;
     if (act) {
       x = need ? ((xn << 16) | w) : xn;
-      out[i] = uint8_t(s);
+      obuf[(t & 15) * K + lane] = uint8_t(s);
     }
     ptr += __popcll(m);
     if (ptr - base >= 64) {
@@ -278,6 +293,17 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
       wa = w1;
       w1 = w2;
       w2 = fetch(base + 128 + lane);
+    }
+    if ((t & 15) == 15 || t + 1 == steps) {
+      // symbols of steps t0..t are output bytes [t0*K, (t+1)*K): contiguous
+      // in obuf; 16-byte groups may run up to 15 bytes past n, which stays
+      // inside the slot (capacities are multiples of 16)
+      __syncthreads();
+      const uint32_t t0 = t & ~15u, have = min((t - t0 + 1) * K, n - t0 * K);
+      if (16 * lane < have)
+        *reinterpret_cast<AX_GLOBAL u32x4*>(out + t0 * K + 16 * lane) =
+            *reinterpret_cast<const u32x4*>(obuf + 16 * lane);
+      __syncthreads();
     }
   }
   bad |= lane < K && x != ax::kRansLow;
@@ -404,7 +430,8 @@ __device__ inline Map4 block_excl_map(const Map4& m, Map4* total, ParseShared& s
 // Decode `count` consecutive LEB128 values starting at byte *cursor of
 // src[0..n) into dst (u64) — all 256 threads. Returns false on a malformed
 // or missing value.  *cursor advances past the last value.
-__device__ bool leb_values(const uint8_t* src, uint32_t n, uint32_t* cursor, uint32_t count, uint64_t* dst,
+template <class Src>
+__device__ bool leb_values(Src src, uint32_t n, uint32_t* cursor, uint32_t count, uint64_t* dst,
                            ParseShared& sh) {
   const uint32_t t = threadIdx.x, lane = lane_id(), wv = t >> 6;
   uint32_t found = 0;
@@ -496,8 +523,11 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
       *reinterpret_cast<uint4*>(sh.lenb + k) = *reinterpret_cast<const uint4*>(lens + k);
   __syncthreads();
   bool failed = sh.bad != 0;
-  const uint8_t* offv = n_off <= kOffStage ? sh.offb : offs;
-  const uint8_t* lenv = n_len <= kLenStage ? sh.lenb : lens;
+  // the streams are read from LDS when staged, else from global memory (two
+  // instantiations, so neither path goes through flat addressing)
+  const bool off_lds = n_off <= kOffStage, len_lds = n_len <= kLenStage;
+  const AX_GLOBAL uint8_t* const offg = gp(offs);
+  const AX_GLOBAL uint8_t* const leng = gp(lens);
 
   uint32_t dst = 0, litp = 0, offc = 0, lenc = 0;
   uint64_t ntok = 0;
@@ -520,13 +550,21 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     const uint32_t n_tokc = uint32_t(ctot >> 48);
     // length and offset values of this chunk
     uint64_t* lv64 = sh.offval;  // reuse: lengths first, then offsets
-    if (!leb_values(lenv, n_len, &lenc, n_esc, lv64, sh)) { failed = true; break; }
+    if (!(len_lds ? leb_values(static_cast<const uint8_t*>(sh.lenb), n_len, &lenc, n_esc, lv64, sh)
+                  : leb_values(leng, n_len, &lenc, n_esc, lv64, sh))) {
+      failed = true;
+      break;
+    }
     if (t < n_esc) {
       const uint64_t e = lv64[t];
       sh.lenval[t] = e > B ? 0xFFFFFFFFu : uint32_t(e);
     }
     __syncthreads();
-    if (!leb_values(offv, n_off, &offc, n_k1, sh.offval, sh)) { failed = true; break; }
+    if (!(off_lds ? leb_values(static_cast<const uint8_t*>(sh.offb), n_off, &offc, n_k1, sh.offval, sh)
+                  : leb_values(offg, n_off, &offc, n_k1, sh.offval, sh))) {
+      failed = true;
+      break;
+    }
     uint32_t len = 0;
     if (valid) {
       const uint32_t ext = esc ? sh.lenval[esc_i] : 0u;
@@ -625,10 +663,10 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     return;
   }
   // write the tile with 16-byte stores (match bytes are filled by the match layer)
-  uint8_t* o = J.out + bs;
+  AX_GLOBAL uint8_t* o = gp(J.out + bs);
   const uint32_t full = blen & ~15u;
   for (uint32_t k = 16 * t; k < full; k += 16 * kParseThreads)
-    *reinterpret_cast<uint4*>(o + k) = *reinterpret_cast<const uint4*>(sh.tile + k);
+    *reinterpret_cast<AX_GLOBAL u32x4*>(o + k) = *reinterpret_cast<const u32x4*>(sh.tile + k);
   for (uint32_t k = full + t; k < blen; k += kParseThreads) o[k] = sh.tile[k];
 }
 
@@ -653,7 +691,9 @@ struct CopyArgs {
   uint32_t* long_cnt;
   uint32_t round;
   DevStatus* st;
-  uint32_t n_chunks;
+  uint32_t* pbits;           // the last round's leftovers, one bit per token
+  const uint32_t* plist;     // the same tokens, ascending (the persistent finish's work)
+  int mark;                  // this round is the last: mark leftovers in pbits
   uint64_t spin_limit;
   int serial;
   int fill_round, fill_tail;  // kFillLaneWave or kFillSegmented
@@ -679,9 +719,14 @@ __device__ inline void find_cover(const CopyArgs& a, const WinBlock& wb, uint32_
   const uint64_t sb = s0 / B;
   const uint32_t job_end = wb.first + wb.count;
   uint32_t x = wb.first, y = job_end;
-  while (x < y) {  // first window block of the job with b >= sb
-    const uint32_t mid = (x + y) >> 1;
-    if (a.wbl[mid].b < sb) x = mid + 1; else y = mid;
+  const uint64_t b0 = a.wbl[wb.first].b;
+  if (sb >= b0 && sb - b0 < wb.count && a.wbl[wb.first + uint32_t(sb - b0)].b == sb) {
+    x = wb.first + uint32_t(sb - b0);  // the job's blocks are consecutive up to sb (whole-archive windows)
+  } else {
+    while (x < y) {  // first window block of the job with b >= sb
+      const uint32_t mid = (x + y) >> 1;
+      if (a.wbl[mid].b < sb) x = mid + 1; else y = mid;
+    }
   }
   const uint32_t end_tok = job_end < a.n_items ? a.wbl[job_end].tok : a.n_tok;
   uint32_t p = x < job_end ? a.wbl[x].tok : end_tok;
@@ -699,15 +744,16 @@ __device__ inline void find_cover(const CopyArgs& a, const WinBlock& wb, uint32_
 }
 
 // The output base of token t's archive.
-__device__ inline uint8_t* token_out(const CopyArgs& a, uint32_t t) { return a.jobs[a.wbl[a.tblk[t]].job].out; }
+typedef AX_GLOBAL uint8_t* gbytes;
+__device__ inline gbytes token_out(const CopyArgs& a, uint32_t t) { return gp(a.jobs[a.wbl[a.tblk[t]].job].out); }
 
 template <bool COH>
-__device__ inline uint8_t ldb(const uint8_t* p) {
+__device__ inline uint8_t ldb(const AX_GLOBAL uint8_t* p) {
   if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   else return *p;
 }
 template <bool COH>
-__device__ inline void stb(uint8_t* p, uint8_t v) {
+__device__ inline void stb(gbytes p, uint8_t v) {
   if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   else *p = v;
 }
@@ -715,7 +761,7 @@ __device__ inline void stb(uint8_t* p, uint8_t v) {
 // The serial ablation: one lane, byte after byte, reading the bytes it may
 // itself have just written (a self-overlapping match is a dependency chain).
 template <bool COH>
-__device__ inline void fill_serial(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len) {
+__device__ inline void fill_serial(gbytes out, uint64_t dst, uint64_t src, uint32_t len) {
   for (uint32_t k = 0; k < len; ++k) {
     stb<COH>(out + dst + k, ldb<COH>(out + src + k));
     __builtin_amdgcn_s_waitcnt(0x0F70);  // the next load may read this byte
@@ -726,7 +772,7 @@ __device__ inline void fill_serial(uint8_t* out, uint64_t dst, uint64_t src, uin
 // then sixteen stores.  The source index runs over the period dist (for
 // dist >= len it never wraps and the fill is a plain copy).
 template <bool COH>
-__device__ inline void fill_lane(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len) {
+__device__ inline void fill_lane(gbytes out, uint64_t dst, uint64_t src, uint32_t len) {
   const uint64_t dist = dst - src;
   uint64_t j = 0;
   for (uint32_t k0 = 0; k0 < len; k0 += 16) {
@@ -747,7 +793,7 @@ __device__ inline void fill_lane(uint8_t* out, uint64_t dst, uint64_t src, uint3
 
 // The whole wave fills one long token: eight bytes per lane in flight.
 template <bool COH>
-__device__ inline void fill_wave(uint8_t* out, uint64_t dst, uint64_t src, uint32_t len, uint32_t lane) {
+__device__ inline void fill_wave(gbytes out, uint64_t dst, uint64_t src, uint32_t len, uint32_t lane) {
   const uint64_t dist = dst - src;
   const uint64_t step = 64 % dist;
   uint64_t j = lane % dist;
@@ -777,7 +823,7 @@ struct FillStage {
   uint32_t len[64];
   uint64_t dst[64];
   uint64_t src[64];
-  uint8_t* out[64];
+  gbytes out[64];
 };
 
 constexpr uint32_t kFillBytes = 8;  // consecutive bytes per lane per pass
@@ -789,7 +835,7 @@ enum { kFillLaneWave = 0, kFillSegmented = 1 };
 // whatever the mix of short and long tokens.  Byte k of a token comes from
 // src + (k mod dist) (dist >= len: a plain copy).
 template <bool COH>
-__device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64_t src, uint32_t len, int serial,
+__device__ inline void fill_ready(gbytes out, bool ready, uint64_t dst, uint64_t src, uint32_t len, int serial,
                                   int fill_mode, FillStage& fs) {
   const uint32_t lane = lane_id();
   if (serial) {
@@ -803,7 +849,7 @@ __device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64
     while (lm) {
       const int l = __builtin_ctzll(lm);
       lm &= lm - 1;
-      uint8_t* const o = reinterpret_cast<uint8_t*>(__shfl((unsigned long long)reinterpret_cast<uintptr_t>(out), l, 64));
+      const gbytes o = reinterpret_cast<gbytes>(__shfl((unsigned long long)reinterpret_cast<uintptr_t>(out), l, 64));
       fill_wave<COH>(o, __shfl((unsigned long long)dst, l, 64), __shfl((unsigned long long)src, l, 64),
                      __shfl(len, l, 64), lane);
     }
@@ -831,7 +877,7 @@ __device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64
         if (fs.end[l + step - 1] <= f0) l += step;
       uint32_t e = fs.end[l], start = e - fs.len[l];
       uint64_t d = fs.dst[l], sr = fs.src[l], dist = d - sr;
-      uint8_t* o = fs.out[l];
+      gbytes o = fs.out[l];
       uint64_t k = f0 - start;  // < 2^16: a token lies inside one block
       uint64_t j = dist > k ? k : uint64_t(uint32_t(k) % uint32_t(dist));
 #pragma unroll
@@ -852,10 +898,10 @@ __device__ inline void fill_ready(uint8_t* out, bool ready, uint64_t dst, uint64
       }
 #pragma unroll
       for (uint32_t q = 0; q < kFillBytes; ++q)
-        v[q] = to[q] != ~0ull ? ldb<COH>(reinterpret_cast<const uint8_t*>(at[q])) : uint8_t(0);
+        v[q] = to[q] != ~0ull ? ldb<COH>(reinterpret_cast<const AX_GLOBAL uint8_t*>(at[q])) : uint8_t(0);
 #pragma unroll
       for (uint32_t q = 0; q < kFillBytes; ++q)
-        if (to[q] != ~0ull) stb<COH>(reinterpret_cast<uint8_t*>(to[q]), v[q]);
+        if (to[q] != ~0ull) stb<COH>(reinterpret_cast<gbytes>(to[q]), v[q]);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -904,12 +950,12 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     }
     uint64_t src = 0, dst = 0;
     uint32_t len = 0, lo = 0, cnt = 0;
-    uint8_t* out = nullptr;
+    gbytes out = nullptr;
     if (act) {
       token_at(a.tok, t, src, dst, len);
       const WinBlock wb = a.wbl[a.tblk[t]];
       const JobDev& J = a.jobs[wb.job];
-      out = J.out;
+      out = gp(J.out);
       if (FIRST) {
         const uint64_t dist = dst - src;
         find_cover(a, wb, J.B, src, src + (dist < len ? dist : len), lo, cnt);
@@ -936,6 +982,16 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     if (ready && !split) a.done[t] = uint8_t(a.round);
     const bool left = act && !ready;
     const uint64_t m = __ballot(left);
+    if (FIRST) {
+      // round 0: a wave holds 64 consecutive tokens (64-aligned), so it owns
+      // two bitmap words; it writes its leftovers there when this round is
+      // the last, else clears them for the last round's marks
+      if ((lane & 31) == 0 && act) a.pbits[t >> 5] = a.mark ? uint32_t(m >> (lane & 32)) : 0u;
+      if (a.mark) continue;
+    } else if (a.mark) {
+      if (left) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+      continue;
+    }
     if (m) {  // leftovers go to this workgroup's sublist (counters spread over kSub addresses)
       uint32_t at = 0;
       if (lane == 0) at = atomicAdd(a.cnt_out + my_sub * kCounterStride, uint32_t(__popcll(m)));
@@ -956,7 +1012,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_long(CopyArgs a) {
     uint64_t src, dst;
     uint32_t len;
     token_at(a.tok, t, src, dst, len);
-    uint8_t* const out = token_out(a, t);
+    const gbytes out = token_out(a, t);
     const uint64_t dist = dst - src;
     const uint64_t step = uint64_t(kCopyThreads) % dist;
     uint64_t j = threadIdx.x % dist;
@@ -980,31 +1036,92 @@ __global__ __launch_bounds__(kCopyThreads) void k_long(CopyArgs a) {
   }
 }
 
-// Persistent finish: 64-token chunks in output order by ticket; each wave
-// polls its unfinished tokens' covering tokens and copies a token once they
-// are all done.  Output bytes and done flags use agent-coherent accesses and
-// a store-completion wait precedes each done flag, so a flag seen by another
-// XCD implies its bytes are visible there.  A token waits only on
-// lower-indexed tokens, which lower tickets hold, so every wait ends.
+// Compaction of the last round's leftovers into an ascending list: per
+// workgroup of 1024 bitmap words, a population count, then the scatter.
+constexpr uint32_t kPackWords = 4 * kCopyThreads;
+
+__device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
+  uint32_t tot;
+  const uint32_t ex = wave_excl_sum(v, &tot);
+  (void)ex;
+  if (lane_id() == 0) red[threadIdx.x >> 6] = tot;
+  __syncthreads();
+  uint32_t s = 0;
+  for (uint32_t k = 0; k < kCopyThreads / 64; ++k) s += red[k];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(kCopyThreads) void k_pcount(const uint32_t* pbits, uint32_t n_words, uint32_t* pcnt) {
+  __shared__ uint32_t red[kCopyThreads / 64];
+  uint32_t c = 0;
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t w = blockIdx.x * kPackWords + k * kCopyThreads + threadIdx.x;
+    if (w < n_words) c += __popc(pbits[w]);
+  }
+  const uint32_t s = block_sum_u32(c, red);
+  if (threadIdx.x == 0) pcnt[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kCopyThreads) void k_pscatter(const uint32_t* pbits, uint32_t n_words,
+                                                           const uint32_t* pcnt, uint32_t* plist, DevStatus* st) {
+  __shared__ uint32_t red[kCopyThreads / 64];
+  uint32_t before = 0;
+  for (uint32_t g = threadIdx.x; g < blockIdx.x; g += kCopyThreads) before += pcnt[g];
+  const uint32_t base = block_sum_u32(before, red);
+  // thread i takes words 4i..4i+3 of the workgroup's range (consecutive)
+  uint32_t wv[4], c = 0;
+  const uint32_t w0 = blockIdx.x * kPackWords + 4 * threadIdx.x;
+  for (uint32_t k = 0; k < 4; ++k) {
+    wv[k] = w0 + k < n_words ? pbits[w0 + k] : 0u;
+    c += __popc(wv[k]);
+  }
+  uint32_t wtot;
+  const uint32_t wex = wave_excl_sum(c, &wtot);
+  if (lane_id() == 0) red[threadIdx.x >> 6] = wtot;
+  __syncthreads();
+  uint32_t at = base + wex;
+  for (uint32_t k = 0; k < (threadIdx.x >> 6); ++k) at += red[k];
+  for (uint32_t k = 0; k < 4; ++k) {
+    uint32_t bits = wv[k];
+    while (bits) {
+      const uint32_t j = __builtin_ctz(bits);
+      bits &= bits - 1;
+      plist[at++] = (w0 + k) * 32 + j;
+    }
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kCopyThreads - 1) st->n_pending = at;
+}
+
+// Persistent finish over the compacted leftovers: 64-token chunks of the
+// ascending list by ticket; each wave polls its unfinished tokens' covering
+// tokens and copies a token once they are all done.  Output bytes and done
+// flags use agent-coherent accesses and a store-completion wait precedes
+// each done flag, so a flag seen by another XCD implies its bytes are visible
+// there.  A token waits only on lower-indexed tokens, which are done or sit
+// in lower chunks whose tickets running waves hold, so every wait ends.
 __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
   __shared__ FillStage stage[kCopyThreads / 64];
   const uint32_t lane = lane_id();
   FillStage& fs = stage[threadIdx.x >> 6];
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const uint32_t per = a.tail_chunks;  // consecutive chunks per ticket
-  const uint32_t n_tickets = (a.n_chunks + per - 1) / per;
+  const uint32_t n_pend = a.st->n_pending;
+  const uint32_t n_chunks = (n_pend + 63) / 64;
+  const uint32_t n_tickets = (n_chunks + per - 1) / per;
   for (;;) {
     uint32_t tk = 0;
     if (lane == 0) tk = atomicAdd(&a.st->ticket, 1u);
     tk = __shfl(tk, 0, 64);
     if (tk >= n_tickets) return;
-    for (uint32_t chunk = tk * per; chunk < min(tk * per + per, a.n_chunks); ++chunk) {
-      const uint32_t t = chunk * 64 + lane;
-      bool pending = t < a.n_tok && a.done[t] == kPending;
+    for (uint32_t chunk = tk * per; chunk < min(tk * per + per, n_chunks); ++chunk) {
+      const uint32_t li = chunk * 64 + lane;
+      const uint32_t t = li < n_pend ? a.plist[li] : 0u;
+      bool pending = li < n_pend;
       if (!__ballot(pending)) continue;
       uint64_t src = 0, dst = 0;
       uint32_t len = 0, lo = 0, cnt = 0;
-      uint8_t* out = nullptr;
+      gbytes out = nullptr;
       if (pending) {
         token_at(a.tok, t, src, dst, len);
         out = token_out(a, t);
@@ -1047,6 +1164,7 @@ __global__ void k_window_init(DevStatus* st) {
   if (threadIdx.x == 0) {
     st->ticket = 0;
     st->long_count = 0;
+    st->n_pending = 0;
   }
 }
 
@@ -1063,7 +1181,8 @@ inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 namespace ax {
 
 struct Layout {
-  uint64_t status, nsym, lit, cmd, off, len, tok, tblk, cov, done, counts, list0, list1, llist, total;
+  uint64_t status, nsym, lit, cmd, off, len, tok, tblk, cov, done, counts, list0, list1, llist, pbits, pcnt, plist,
+      total;
   uint64_t sub_cap;
 };
 
@@ -1137,6 +1256,9 @@ static Layout make_layout(const Plan& P) {
   L.list0 = at, at = align256(at + 4 * kSub * L.sub_cap);
   L.list1 = at, at = align256(at + 4 * kSub * L.sub_cap);
   L.llist = at, at = align256(at + 4 * T);
+  L.pbits = at, at = align256(at + 4 * ((T + 31) / 32 + 64));
+  L.pcnt = at, at = align256(at + 4 * ((T + 31) / 32 / kPackWords + 1));
+  L.plist = at, at = align256(at + 4 * T);
   L.total = at;
   return L;
 }
@@ -1474,8 +1596,10 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
       CopyArgs ca{P->d_jobs, wbl, W.items, reinterpret_cast<const uint64_t*>(w + L.tok),
                   reinterpret_cast<const uint32_t*>(w + L.tblk), ntok, reinterpret_cast<uint32_t*>(w + L.cov),
                   w + L.done, nullptr, lists[0], nullptr, cset(0), cset(1), uint32_t(L.sub_cap),
-                  reinterpret_cast<uint32_t*>(w + L.llist), &st->long_count, 0, st, (ntok + 63) / 64, 1ull << 22,
-                  copy_mode == AX_COPY_SERIAL, P->opt.fill_round, P->opt.fill_tail, uint32_t(P->opt.tail_chunks)};
+                  reinterpret_cast<uint32_t*>(w + L.llist), &st->long_count, 0, st,
+                  reinterpret_cast<uint32_t*>(w + L.pbits), reinterpret_cast<const uint32_t*>(w + L.plist),
+                  P->opt.bulk_rounds <= 1, 1ull << 22, copy_mode == AX_COPY_SERIAL, P->opt.fill_round,
+                  P->opt.fill_tail, uint32_t(P->opt.tail_chunks)};
       const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
       hipLaunchKernelGGL(k_round<true>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       hipLaunchKernelGGL(k_long, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
@@ -1486,10 +1610,16 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
         ca.cnt_in = cset(r - 1);
         ca.cnt_out = cset(r);
         ca.cnt_clear = cset(r + 1);
+        ca.mark = r + 1 == P->opt.bulk_rounds;
         // later rounds see the previous round's leftovers only: a smaller grid
         hipLaunchKernelGGL(k_round<false>, dim3(std::min<uint32_t>(grid, 512)), dim3(kCopyThreads), 0, s, ca);
       }
       ca.round = uint32_t(P->opt.bulk_rounds);
+      const uint32_t n_words = (ntok + 31) / 32, pgrid = (n_words + kPackWords - 1) / kPackWords;
+      uint32_t* pcnt = reinterpret_cast<uint32_t*>(w + L.pcnt);
+      hipLaunchKernelGGL(k_pcount, dim3(pgrid), dim3(kCopyThreads), 0, s, ca.pbits, n_words, pcnt);
+      hipLaunchKernelGGL(k_pscatter, dim3(pgrid), dim3(kCopyThreads), 0, s, ca.pbits, n_words, pcnt,
+                         reinterpret_cast<uint32_t*>(w + L.plist), st);
       const uint64_t waves = (ntok + 64ull * P->opt.tail_chunks - 1) / (64ull * P->opt.tail_chunks);
       const uint32_t tgrid = uint32_t(std::min<uint64_t>((waves + 3) / 4, uint64_t(P->copy_grid)));
       hipLaunchKernelGGL(k_tail, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);

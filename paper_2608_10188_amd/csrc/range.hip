@@ -133,16 +133,43 @@ int union_closure(const aceapex_decoder* d, uint32_t n, const uint64_t* offs, co
 }
 
 // Copy range bytes from the full-size scratch output to each caller buffer.
+// Every range is cut into 4 KiB chunks numbered across the batch (chunk0 is a
+// range's first chunk); a workgroup copies one chunk, each thread sixteen
+// bytes with all loads issued before the stores, so wide ranges spread over
+// the whole device and every byte instruction of a wave covers 64
+// consecutive bytes.  Source and destination alignments are arbitrary.
+constexpr uint32_t kGatherThreads = 256;
+constexpr uint32_t kGatherChunk = 16 * kGatherThreads;
+
 struct GatherDesc {
   const uint8_t* src;
   uint8_t* dst;
   uint64_t len;
+  uint64_t chunk0;
 };
 
-__global__ void k_gather(const GatherDesc* desc, uint32_t n) {
-  for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
-    const GatherDesc g = desc[r];
-    for (uint64_t k = threadIdx.x; k < g.len; k += blockDim.x) g.dst[k] = g.src[k];
+__global__ __launch_bounds__(kGatherThreads) void k_gather(const GatherDesc* desc, uint32_t n, uint64_t chunks) {
+  for (uint64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    uint32_t lo = 0, hi = n - 1;  // last range whose first chunk is <= c
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (desc[mid].chunk0 <= c) lo = mid; else hi = mid - 1;
+    }
+    const GatherDesc g = desc[lo];
+    const __attribute__((address_space(1))) uint8_t* src = (const __attribute__((address_space(1))) uint8_t*)g.src;
+    __attribute__((address_space(1))) uint8_t* dst = (__attribute__((address_space(1))) uint8_t*)g.dst;
+    const uint64_t base = (c - g.chunk0) * kGatherChunk + threadIdx.x;
+    uint8_t v[16];
+#pragma unroll
+    for (uint32_t q = 0; q < 16; ++q) {
+      const uint64_t k = base + q * kGatherThreads;
+      v[q] = k < g.len ? src[k] : uint8_t(0);
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < 16; ++q) {
+      const uint64_t k = base + q * kGatherThreads;
+      if (k < g.len) dst[k] = v[q];
+    }
   }
 }
 
@@ -278,10 +305,16 @@ int aceapex_decode_ranges(aceapex_range_plan* rp, uint32_t n, const uint64_t* of
       if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&rp->h_desc), sizeof(GatherDesc) * rp->desc_cap);
       if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
     }
-    for (uint32_t i = 0; i < n; ++i) rp->h_desc[i] = GatherDesc{d_full + offs[i], d_outs[i], lens[i]};
+    uint64_t chunks = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      rp->h_desc[i] = GatherDesc{d_full + offs[i], d_outs[i], lens[i], chunks};
+      chunks += (lens[i] + kGatherChunk - 1) / kGatherChunk;
+    }
     hipError_t e = hipMemcpyAsync(rp->d_desc, rp->h_desc, sizeof(GatherDesc) * n, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
-    hipLaunchKernelGGL(k_gather, dim3(std::min<uint32_t>(n, 4096)), dim3(256), 0, s, rp->d_desc, n);
+    if (chunks)
+      hipLaunchKernelGGL(k_gather, dim3(uint32_t(std::min<uint64_t>(chunks, 8192))), dim3(kGatherThreads), 0, s,
+                         rp->d_desc, n, chunks);
     e = hipGetLastError();
     if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
   }

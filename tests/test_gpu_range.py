@@ -87,6 +87,28 @@ def test_decode_ranges_match_original(dna_archive):
             assert np.array_equal(o[:ln].cpu().numpy(), x[off:off + ln]), (off, ln)
 
 
+def test_decode_ranges_into_unaligned_views(dna_archive):
+    """Outputs that are views of one buffer at odd offsets (as a server packs
+    them), ranges of 1 B to several 4 KiB gather chunks."""
+    x, arc = dna_archive
+    d, full = _decoder_with_index(arc)
+    rp = ax.RangePlan(d, max_blocks=512, max_tokens=1 << 18)
+    work = torch.empty(rp.workspace_bytes, dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(12)
+    lens = [1, 3, 4095, 4096, 4097, 12289, 70001, 16384, 5, 200000]
+    offs = [int(rng.integers(0, x.size - ln)) for ln in lens]
+    _say("unaligned views", len(lens))
+    buf = torch.full((sum(lens) + 7,), 0xCC, dtype=torch.uint8, device="cuda")
+    outs = list(torch.split(buf[7:], lens))
+    rp.decode(offs, lens, outs, full, work)
+    got = buf.cpu().numpy()
+    assert (got[:7] == 0xCC).all()
+    at = 7
+    for off, ln in zip(offs, lens):
+        assert np.array_equal(got[at: at + ln], x[off: off + ln]), (off, ln)
+        at += ln
+
+
 def test_block_straddling_sweep(dna_archive):
     x, arc = dna_archive
     d, full = _decoder_with_index(arc)
