@@ -59,7 +59,6 @@ constexpr uint8_t kPending = 0xFF;          // done[] value of a token not yet c
 constexpr uint32_t kSub = 64;               // pending-list sublists (one counter each, 256 B apart)
 constexpr uint32_t kCounterStride = 64;     // u32 between two sublist counters
 constexpr uint32_t kMaxRoundGrid = 4096;    // workgroups of a round launch
-constexpr uint64_t kTagRef = 1ull << 63;    // history-map slot holding an input index
 
 struct DevStatus {
   int32_t err;
@@ -331,37 +330,30 @@ struct ParseArgs {
   DevStatus* st;
 };
 
-struct Map4 {  // history map: slot = kTagRef | input index, or a distance
-  uint64_t s[4];
-};
+// History maps.  A command acts on the four-entry distance history as a map
+// from the history before it to the history after it; a run of commands
+// composes these maps.  Each of the four output slots names where its
+// distance comes from: an input slot j (kFromIn | j) or the explicit match at
+// chunk position c (its distance is cdist[c]).  The four 16-bit slot codes
+// pack into one u64, so a scan step moves one 64-bit value per lane.
+constexpr uint32_t kFromIn = 0x8000;
+constexpr uint64_t kMapId = uint64_t(kFromIn | 0) | (uint64_t(kFromIn | 1) << 16) | (uint64_t(kFromIn | 2) << 32) |
+                            (uint64_t(kFromIn | 3) << 48);
 
-__device__ inline uint64_t map_pick(const Map4& f, uint64_t g) {
-  if (!(g & kTagRef)) return g;
-  const uint32_t j = uint32_t(g & 3);
-  return j == 0 ? f.s[0] : j == 1 ? f.s[1] : j == 2 ? f.s[2] : f.s[3];
-}
+__device__ inline uint32_t map_slot(uint64_t m, uint32_t i) { return uint32_t(m >> (16 * i)) & 0xFFFFu; }
 // (later g) after (earlier f)
-__device__ inline Map4 map_after(const Map4& g, const Map4& f) {
-  Map4 h;
+__device__ inline uint64_t map_after(uint64_t g, uint64_t f) {
+  uint64_t h = 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) h.s[i] = map_pick(f, g.s[i]);
+  for (uint32_t i = 0; i < 4; ++i) {
+    const uint32_t gi = map_slot(g, i);
+    const uint32_t v = (gi & kFromIn) ? map_slot(f, gi & 3) : gi;
+    h |= uint64_t(v) << (16 * i);
+  }
   return h;
 }
 __device__ inline uint64_t pick4(const uint64_t h[4], uint64_t j) {
   return j == 0 ? h[0] : j == 1 ? h[1] : j == 2 ? h[2] : h[3];
-}
-__device__ inline Map4 map_identity() { return Map4{{kTagRef | 0, kTagRef | 1, kTagRef | 2, kTagRef | 3}}; }
-__device__ inline Map4 map_shfl_up(const Map4& m, int o) {
-  Map4 r;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) r.s[i] = __shfl_up((unsigned long long)m.s[i], o, 64);
-  return r;
-}
-__device__ inline Map4 map_shfl(const Map4& m, int src) {
-  Map4 r;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) r.s[i] = __shfl((unsigned long long)m.s[i], src, 64);
-  return r;
 }
 
 struct ParseShared {
@@ -374,7 +366,9 @@ struct ParseShared {
   uint64_t offval[kParseThreads];
   uint32_t lenval[kParseThreads];
   uint64_t wsum[4][2];
-  Map4 wmap[4];
+  uint64_t wmap[4];
+  uint64_t cdist[kParseThreads];  // distance of the explicit match at each chunk position
+  uint64_t last4[4];              // the chunk's last explicit-match distances, newest first
   uint32_t wterm[4];
   int32_t wlast[4];
   uint32_t leb_found, leb_cursor;
@@ -405,26 +399,25 @@ __device__ inline uint64_t block_excl_sum64(uint64_t v, uint64_t* total, ParseSh
 
 // Block-wide exclusive scan of history maps; returns the map before this
 // command and the chunk's total map.
-__device__ inline Map4 block_excl_map(const Map4& m, Map4* total, ParseShared& sh) {
+__device__ inline uint64_t block_excl_map(uint64_t m, uint64_t* total, ParseShared& sh) {
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  Map4 x = m;
+  uint64_t x = m;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    Map4 y = map_shfl_up(x, o);
+    const uint64_t y = __shfl_up((unsigned long long)x, o, 64);
     if (lane >= (uint32_t)o) x = map_after(x, y);
   }
   if (lane == 63) sh.wmap[wv] = x;
   __syncthreads();
-  Map4 pre = map_identity(), tot = map_identity();
+  uint64_t pre = kMapId, tot = kMapId;
   for (uint32_t k = 0; k < 4; ++k) {
     if (k < wv) pre = map_after(sh.wmap[k], pre);
     tot = map_after(sh.wmap[k], tot);
   }
   __syncthreads();
   *total = tot;
-  Map4 incl_prev = map_shfl_up(x, 1);  // inclusive of the previous lane
-  Map4 ex = lane == 0 ? map_identity() : incl_prev;
-  return map_after(ex, pre);
+  const uint64_t incl_prev = __shfl_up((unsigned long long)x, 1, 64);  // inclusive of the previous lane
+  return map_after(lane == 0 ? kMapId : incl_prev, pre);
 }
 
 // Decode `count` consecutive LEB128 values starting at byte *cursor of
@@ -580,26 +573,40 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     if (is0 && uint64_t(clit) + len > n_lit) bad = true;
     const uint64_t absdst = bs + cdst;
     uint64_t src = 0;
-    Map4 mine = map_identity();
     if (is1) {
       src = sh.offval[k1_i];
       if (src >= absdst) bad = true;
-      else mine = Map4{{absdst - src, kTagRef | 0, kTagRef | 1, kTagRef | 2}};
-    } else if (is2) {
-      const uint32_t r = (c >> 2) & 3;
-      mine.s[0] = kTagRef | r;
-      mine.s[1] = kTagRef | (r >= 1 ? 0u : 1u);
-      mine.s[2] = kTagRef | (r >= 2 ? 1u : 2u);
-      mine.s[3] = kTagRef | (r >= 3 ? 2u : 3u);
+      else sh.cdist[t] = absdst - src;
     }
-    Map4 mtot;
-    const Map4 before = block_excl_map(mine, &mtot, sh);
-    if (is2) {
-      const uint32_t r = (c >> 2) & 3;
-      const uint64_t g = pick4(before.s, r);
-      const uint64_t d = (g & kTagRef) ? pick4(hist, g & 3) : g;
-      if (d > absdst) bad = true;
-      else src = absdst - d;
+    const uint32_t n_rep = n_tokc - n_k1;
+    uint64_t nh[4];
+    if (n_rep) {  // repeat matches read the history: scan the command maps
+      uint64_t mine = kMapId;
+      if (is1) {
+        mine = uint64_t(t) | (uint64_t(kFromIn | 0) << 16) | (uint64_t(kFromIn | 1) << 32) |
+               (uint64_t(kFromIn | 2) << 48);
+      } else if (is2) {
+        const uint32_t r = (c >> 2) & 3;
+        mine = uint64_t(kFromIn | r) | (uint64_t(kFromIn | (r >= 1 ? 0u : 1u)) << 16) |
+               (uint64_t(kFromIn | (r >= 2 ? 1u : 2u)) << 32) | (uint64_t(kFromIn | (r >= 3 ? 2u : 3u)) << 48);
+      }
+      uint64_t mtot;
+      const uint64_t before = block_excl_map(mine, &mtot, sh);  // also orders the cdist writes
+      if (is2) {
+        const uint32_t g = map_slot(before, (c >> 2) & 3);
+        const uint64_t d = (g & kFromIn) ? pick4(hist, g & 3) : sh.cdist[g];
+        if (d > absdst) bad = true;
+        else src = absdst - d;
+      }
+      for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t g = map_slot(mtot, k);
+        nh[k] = (g & kFromIn) ? pick4(hist, g & 3) : sh.cdist[g];
+      }
+    } else {  // explicit matches only: the history takes their last distances
+      if (is1 && !bad && k1_i + 4 >= n_k1) sh.last4[n_k1 - 1 - k1_i] = absdst - src;
+      __syncthreads();
+      const uint32_t m4 = min(n_k1, 4u);
+      for (uint32_t k = 0; k < 4; ++k) nh[k] = k < m4 ? sh.last4[k] : pick4(hist, k - m4);
     }
     if ((is1 || is2) && !bad) {
       const uint64_t gi = ntok + tok_i;
@@ -653,8 +660,6 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     dst += uint32_t(ptot & 0xFFFFFFFFu);
     litp += chunk_lit;
     ntok += n_tokc;
-    uint64_t nh[4];
-    for (int k = 0; k < 4; ++k) nh[k] = (mtot.s[k] & kTagRef) ? pick4(hist, mtot.s[k] & 3) : mtot.s[k];
     for (int k = 0; k < 4; ++k) hist[k] = nh[k];
   }
   if (!failed && (dst != blen || litp != n_lit || lenc != n_len || offc != n_off || ntok != tok_n)) failed = true;
