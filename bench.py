@@ -49,6 +49,8 @@ def parse_args():
     ap.add_argument("--autotune", action="store_true", help="batched workload: tune knobs per size class")
     ap.add_argument("--copy", default="periodic", choices=["periodic", "serial"])
     ap.add_argument("--no-rep", action="store_true")
+    ap.add_argument("--syms-per-lane", type=int, default=0,
+                    help="encoder rANS lane rule S (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--threads", type=int, default=16, help="encoder threads (0 = all)")
     ap.add_argument("--reads", type=int, default=1000, help="closed-loop 16 KiB reads after the timed steps")
@@ -349,7 +351,8 @@ def main():
     x = synth.dna(n, seed) if gen == "dna" else synth.text(n, seed)
     log(f"generated {n} B in {time.time() - t0:.1f}s")
     t0 = time.time()
-    arc, st = ax.encode(x, stats=True, no_rep=int(args.no_rep), threads=args.threads)
+    enc_kw = {"rans_min_syms_per_lane": args.syms_per_lane} if args.syms_per_lane else {}
+    arc, st = ax.encode(x, stats=True, no_rep=int(args.no_rep), threads=args.threads, **enc_kw)
     log(f"encoded to {arc.size} B (ratio {n / arc.size:.3f}) in {time.time() - t0:.1f}s; "
         f"{st.n_commands} commands, {st.n_matches} matches, {st.n_rep} repeats")
     want = xxhash.xxh3_64_intdigest(x.tobytes())

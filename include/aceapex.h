@@ -64,7 +64,7 @@ const char* aceapex_last_error(void);
  *                          depth section (0)
  *   hash_bits              hash-chain head table size (22)
  *   chain_depth            candidates walked per position (32)
- *   rans_min_syms_per_lane S of the rANS lane rule (128)
+ *   rans_min_syms_per_lane S of the rANS lane rule (32)
  *   off_cost_q             an explicit-offset match must be at least
  *                          min_match + ceil(off_cost_q * (LEB128 bytes of its
  *                          offset) / 4) long: the offset's cost in quarter

@@ -62,7 +62,7 @@ void axo_params_default(axo_params* p) {
   p->depth_cap = 0;
   p->hash_bits = 22;
   p->chain_depth = 32;
-  p->rans_min_syms_per_lane = 128;
+  p->rans_min_syms_per_lane = 32;
   p->off_cost_q = 6;
   p->window_log = 0;
 }

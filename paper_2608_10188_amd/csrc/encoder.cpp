@@ -287,7 +287,7 @@ void aceapex_encode_params_default(aceapex_encode_params* p) {
   p->depth_cap = 0;
   p->hash_bits = 22;
   p->chain_depth = 32;
-  p->rans_min_syms_per_lane = 128;
+  p->rans_min_syms_per_lane = 32;
   p->off_cost_q = 6;
   p->window_log = 0;
   p->threads = 0;
