@@ -1616,8 +1616,8 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
         ca.cnt_out = cset(r);
         ca.cnt_clear = cset(r + 1);
         ca.mark = r + 1 == P->opt.bulk_rounds;
-        // later rounds see the previous round's leftovers only: a smaller grid
-        hipLaunchKernelGGL(k_round<false>, dim3(std::min<uint32_t>(grid, 512)), dim3(kCopyThreads), 0, s, ca);
+        // later rounds see the previous round's leftovers only
+        hipLaunchKernelGGL(k_round<false>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       }
       ca.round = uint32_t(P->opt.bulk_rounds);
       const uint32_t n_words = (ntok + 31) / 32, pgrid = (n_words + kPackWords - 1) / kPackWords;
