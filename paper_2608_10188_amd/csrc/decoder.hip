@@ -333,24 +333,21 @@ struct ParseArgs {
 // History maps.  A command acts on the four-entry distance history as a map
 // from the history before it to the history after it; a run of commands
 // composes these maps.  Each of the four output slots names where its
-// distance comes from: an input slot j (kFromIn | j) or the explicit match at
-// chunk position c (its distance is cdist[c]).  The four 16-bit slot codes
-// pack into one u64, so a scan step moves one 64-bit value per lane.
-constexpr uint32_t kFromIn = 0x8000;
-constexpr uint64_t kMapId = uint64_t(kFromIn | 0) | (uint64_t(kFromIn | 1) << 16) | (uint64_t(kFromIn | 2) << 32) |
-                            (uint64_t(kFromIn | 3) << 48);
+// distance comes from: an input slot j, or the explicit match at chunk
+// position c (its distance is cdist[c]).  A map is two words: the slot bytes
+// (j or c) and the tag bytes (0xFF: the slot byte is an input slot, 0x00: a
+// chunk position).  Composing two maps is a byte gather, two v_perm_b32.
+struct HMap {
+  uint32_t v, t;
+};
+constexpr HMap kMapId{0x03020100u, 0xFFFFFFFFu};
 
-__device__ inline uint32_t map_slot(uint64_t m, uint32_t i) { return uint32_t(m >> (16 * i)) & 0xFFFFu; }
-// (later g) after (earlier f)
-__device__ inline uint64_t map_after(uint64_t g, uint64_t f) {
-  uint64_t h = 0;
-#pragma unroll
-  for (uint32_t i = 0; i < 4; ++i) {
-    const uint32_t gi = map_slot(g, i);
-    const uint32_t v = (gi & kFromIn) ? map_slot(f, gi & 3) : gi;
-    h |= uint64_t(v) << (16 * i);
-  }
-  return h;
+// (later g) after (earlier f): slot i takes f's slot j where g's slot i reads
+// input j (selector byte j: f's bytes are the permute's low four), else keeps
+// g's own slot i (selector byte 4 + i).
+__device__ inline HMap map_after(HMap g, HMap f) {
+  const uint32_t sel = (g.v & g.t) | (0x07060504u & ~g.t);
+  return HMap{__builtin_amdgcn_perm(g.v, f.v, sel), __builtin_amdgcn_perm(g.t, f.t, sel)};
 }
 __device__ inline uint64_t pick4(const uint64_t h[4], uint64_t j) {
   return j == 0 ? h[0] : j == 1 ? h[1] : j == 2 ? h[2] : h[3];
@@ -366,7 +363,7 @@ struct ParseShared {
   uint64_t offval[kParseThreads];
   uint32_t lenval[kParseThreads];
   uint64_t wsum[4][2];
-  uint64_t wmap[4];
+  HMap wmap[4];
   uint64_t cdist[kParseThreads];  // distance of the explicit match at each chunk position
   uint64_t last4[4];              // the chunk's last explicit-match distances, newest first
   uint32_t wterm[4];
@@ -399,25 +396,35 @@ __device__ inline uint64_t block_excl_sum64(uint64_t v, uint64_t* total, ParseSh
 
 // Block-wide exclusive scan of history maps; returns the map before this
 // command and the chunk's total map.
-__device__ inline uint64_t block_excl_map(uint64_t m, uint64_t* total, ParseShared& sh) {
+__device__ inline HMap map_shfl_up(HMap m, int o) {
+  return HMap{uint32_t(__shfl_up(int(m.v), o, 64)), uint32_t(__shfl_up(int(m.t), o, 64))};
+}
+__device__ inline HMap block_excl_map(HMap m, HMap* total, ParseShared& sh) {
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  uint64_t x = m;
+  HMap x = m;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const uint64_t y = __shfl_up((unsigned long long)x, o, 64);
+    const HMap y = map_shfl_up(x, o);
     if (lane >= (uint32_t)o) x = map_after(x, y);
   }
   if (lane == 63) sh.wmap[wv] = x;
   __syncthreads();
-  uint64_t pre = kMapId, tot = kMapId;
+  HMap pre = kMapId, tot = kMapId;
   for (uint32_t k = 0; k < 4; ++k) {
     if (k < wv) pre = map_after(sh.wmap[k], pre);
     tot = map_after(sh.wmap[k], tot);
   }
   __syncthreads();
   *total = tot;
-  const uint64_t incl_prev = __shfl_up((unsigned long long)x, 1, 64);  // inclusive of the previous lane
+  const HMap incl_prev = map_shfl_up(x, 1);  // inclusive of the previous lane
   return map_after(lane == 0 ? kMapId : incl_prev, pre);
+}
+
+// Distance named by slot k of a map: an input slot of hist, or an explicit
+// match of the chunk.
+__device__ inline uint64_t map_value(HMap m, uint32_t k, const uint64_t hist[4], const ParseShared& sh) {
+  const uint32_t g = (m.v >> (8 * k)) & 0xFFu;
+  return ((m.t >> (8 * k)) & 1u) ? pick4(hist, g & 3) : sh.cdist[g];
 }
 
 // Decode `count` consecutive LEB128 values starting at byte *cursor of
@@ -581,27 +588,22 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     const uint32_t n_rep = n_tokc - n_k1;
     uint64_t nh[4];
     if (n_rep) {  // repeat matches read the history: scan the command maps
-      uint64_t mine = kMapId;
+      HMap mine = kMapId;
       if (is1) {
-        mine = uint64_t(t) | (uint64_t(kFromIn | 0) << 16) | (uint64_t(kFromIn | 1) << 32) |
-               (uint64_t(kFromIn | 2) << 48);
+        mine = HMap{t | 0x02010000u, 0xFFFFFF00u};
       } else if (is2) {
         const uint32_t r = (c >> 2) & 3;
-        mine = uint64_t(kFromIn | r) | (uint64_t(kFromIn | (r >= 1 ? 0u : 1u)) << 16) |
-               (uint64_t(kFromIn | (r >= 2 ? 1u : 2u)) << 32) | (uint64_t(kFromIn | (r >= 3 ? 2u : 3u)) << 48);
+        mine = HMap{r | ((r >= 1 ? 0u : 1u) << 8) | ((r >= 2 ? 1u : 2u) << 16) | ((r >= 3 ? 2u : 3u) << 24),
+                    0xFFFFFFFFu};
       }
-      uint64_t mtot;
-      const uint64_t before = block_excl_map(mine, &mtot, sh);  // also orders the cdist writes
+      HMap mtot;
+      const HMap before = block_excl_map(mine, &mtot, sh);  // also orders the cdist writes
       if (is2) {
-        const uint32_t g = map_slot(before, (c >> 2) & 3);
-        const uint64_t d = (g & kFromIn) ? pick4(hist, g & 3) : sh.cdist[g];
+        const uint64_t d = map_value(before, (c >> 2) & 3, hist, sh);
         if (d > absdst) bad = true;
         else src = absdst - d;
       }
-      for (uint32_t k = 0; k < 4; ++k) {
-        const uint32_t g = map_slot(mtot, k);
-        nh[k] = (g & kFromIn) ? pick4(hist, g & 3) : sh.cdist[g];
-      }
+      for (uint32_t k = 0; k < 4; ++k) nh[k] = map_value(mtot, k, hist, sh);
     } else {  // explicit matches only: the history takes their last distances
       if (is1 && !bad && k1_i + 4 >= n_k1) sh.last4[n_k1 - 1 - k1_i] = absdst - src;
       __syncthreads();
@@ -643,17 +645,24 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     }
     __syncthreads();
     // place the chunk's literal bytes: aligned 16-byte groups of the literal
-    // stream, each byte moved by its run's (output - literal index) delta
+    // stream, each byte moved by its run's (output - literal index) delta; a
+    // group finds its first byte's run once and steps to the next run at
+    // each run start inside the group
     for (uint32_t g = (litp >> 4) + t; g < ((litp + chunk_lit + 15) >> 4); g += kParseThreads) {
       const uint4 q = *reinterpret_cast<const uint4*>(lit + 16 * g);
       const uint32_t word[4] = {q.x, q.y, q.z, q.w};
+      const uint32_t lo = max(16 * g, litp), hi = min(16 * g + 16, litp + chunk_lit);
+      const uint32_t j0 = lo - litp, w0 = j0 >> 5;
+      const uint32_t wa = sh.runbits[w0], wb = w0 + 1 < kMaxB / 32 ? sh.runbits[w0 + 1] : 0u;
+      const uint32_t starts = __builtin_amdgcn_alignbit(wb, wa, j0 & 31);  // bit k: literal j0 + k starts a run
+      uint32_t r = sh.runpre[w0] + __popc(wa & (0xFFFFFFFFu >> (31 - (j0 & 31)))) - 1;
+      uint32_t delta = sh.rundelta[r];
 #pragma unroll
       for (uint32_t k = 0; k < 16; ++k) {
         const uint32_t li = 16 * g + k;
-        if (li < litp || li >= litp + chunk_lit) continue;
-        const uint32_t j = li - litp, w = j >> 5;
-        const uint32_t r = sh.runpre[w] + __popc(sh.runbits[w] & (0xFFFFFFFFu >> (31 - (j & 31)))) - 1;
-        sh.tile[li + sh.rundelta[r]] = uint8_t(word[k >> 2] >> (8 * (k & 3)));
+        if (li < lo || li >= hi) continue;
+        if (li > lo && ((starts >> (li - lo)) & 1u)) delta = sh.rundelta[++r];
+        sh.tile[li + delta] = uint8_t(word[k >> 2] >> (8 * (k & 3)));
       }
     }
     __syncthreads();
