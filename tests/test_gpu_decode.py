@@ -202,6 +202,25 @@ def test_deep_cross_block_chain():
 
 # -------------------------------------------------------------- behaviour --
 
+@pytest.mark.parametrize("opts", [
+    {ax.OPT_BULK_ROUNDS: 1}, {ax.OPT_BULK_ROUNDS: 2, ax.OPT_TAIL_CHUNKS: 4},
+    {ax.OPT_BULK_ROUNDS: 8, ax.OPT_FILL_ROUNDS: 0, ax.OPT_FILL_TAIL: 1},
+    {ax.OPT_BULK_ROUNDS: 3, ax.OPT_FILL_TAIL: 1, ax.OPT_TAIL_CHUNKS: 16}])
+def test_schedule_options_change_no_byte(opts):
+    """Every schedule knob (rounds, fill modes, tickets per chunk run)
+    decodes a deep text archive and a DNA archive to the oracle's bytes."""
+    for name, x in (("text", synth.text(3 << 20, 46)), ("dna", synth.dna(3 << 20, 47))):
+        arc, _ = oracle.encode(x)
+        dec = ax.Decoder(arc, torch.from_numpy(arc).cuda())
+        for k, v in opts.items():
+            dec.set_option(k, v)
+        out = torch.full((x.size,), 0xCC, dtype=torch.uint8, device="cuda")
+        _say("options", name, opts)
+        dec.decode_all(out=out)
+        err, bad = dec.status()
+        assert err == 0, (err, bad)
+        assert np.array_equal(out.cpu().numpy(), x), (name, opts)
+
 def test_repeat_decode_is_deterministic():
     x = synth.text(2 << 20, 43)
     arc, _ = oracle.encode(x)
