@@ -31,6 +31,17 @@ sys.path.insert(0, ROOT)
 METRIC = "decoded GB/s device-resident (254 MB DNA) vs HBM peak; p50/p99 us per 16 KB read"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of each decode kernel on the 254 MB DNA workload, from
+# two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, each scaled by the
+# same counter on a plain 256 MiB device copy in the same run).  They hold only
+# for the kernel source they were taken on (first 16 hex digits of its SHA-256).
+TRAFFIC_SOURCE = "9cf8d58efc7ee830"
+TRAFFIC_MB = {  # read + write, MB per launch
+    "k_ans": 137.9 + 234.7,
+    "k_parse": 242.3 + 324.0,
+    "copy": (395.1 + 125.8) + 3 * (106.9 + 15.6) + (0.1 + 0.1) + (0.4 + 0.0) + (0.4 + 0.2) + (22.6 + 19.9),
+}
+
 WORKLOADS = {
     # name: (generator, bytes, seed, description)
     "dna254": ("dna", 15500 * 16384, 2, "synthetic DNA 253,952,000 B, 15,500 x 16 KiB blocks"),
@@ -49,6 +60,7 @@ def parse_args():
     ap.add_argument("--autotune", action="store_true", help="batched workload: tune knobs per size class")
     ap.add_argument("--copy", default="periodic", choices=["periodic", "serial"])
     ap.add_argument("--no-rep", action="store_true")
+    ap.add_argument("--depth-cap", type=int, default=0, help="encoder depth cap L (0 = none)")
     ap.add_argument("--syms-per-lane", type=int, default=0,
                     help="encoder rANS lane rule S (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -352,6 +364,8 @@ def main():
     log(f"generated {n} B in {time.time() - t0:.1f}s")
     t0 = time.time()
     enc_kw = {"rans_min_syms_per_lane": args.syms_per_lane} if args.syms_per_lane else {}
+    if args.depth_cap:
+        enc_kw["depth_cap"] = args.depth_cap
     arc, st = ax.encode(x, stats=True, no_rep=int(args.no_rep), threads=args.threads, **enc_kw)
     log(f"encoded to {arc.size} B (ratio {n / arc.size:.3f}) in {time.time() - t0:.1f}s; "
         f"{st.n_commands} commands, {st.n_matches} matches, {st.n_rep} repeats")
@@ -441,8 +455,16 @@ def main():
     achieved = alg[dom] / (stages[dom] / 1e3) / 1e9
     kernels = {"ans": "k_ans", "parse": "k_parse",
                "copy": "match layer (k_round x rounds, k_long, k_pcount, k_pscatter, k_tail)"}
+    import hashlib
+
+    src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_2608_10188_amd", "csrc", "decoder.hip"), "rb").read())
+    traffic = None
+    defaults = not (args.no_rep or args.syms_per_lane or args.depth_cap or args.bulk_rounds or args.fill
+                    or args.tail_chunks or args.copy != "periodic")
+    if args.workload == "dna254" and defaults and src_hash.hexdigest()[:16] == TRAFFIC_SOURCE:
+        traffic = int(TRAFFIC_MB["copy" if dom == "copy" else kernels[dom]] * 1e6)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": kernels[dom],
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": kernels[dom],
                 "pipeline_alg_bytes": b_alg,
                 "pipeline_frac": round(b_alg / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 5)}
 
@@ -453,7 +475,8 @@ def main():
         "config": {"workload": desc, "n_bytes": n, "archive_bytes": c_bytes,
                    "ratio": round(n / c_bytes, 4), "blocks": int(dec.info.n_blocks),
                    "commands": int(st.n_commands), "matches": int(st.n_matches), "repeats": int(st.n_rep),
-                   "copy_mode": args.copy, "no_rep": bool(args.no_rep), "bulk_rounds": args.bulk_rounds or 4, "fill": args.fill or "1,0", "tail_chunks": args.tail_chunks or 1},
+                   "copy_mode": args.copy, "no_rep": bool(args.no_rep), "depth_cap": args.depth_cap,
+                   "max_depth": int(st.max_depth) if args.depth_cap else None, "bulk_rounds": args.bulk_rounds or 4, "fill": args.fill or "1,0", "tail_chunks": args.tail_chunks or 1},
         "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 5),
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         "stage_share": {k: round(v / max(1e-9, sum(stages.values())), 4) for k, v in stages.items()},
