@@ -921,70 +921,50 @@ __device__ inline void fill_ready(gbytes out, bool ready, uint64_t dst, uint64_t
   __builtin_amdgcn_wave_barrier();
 }
 
-// Level-synchronous round r.  Round 0 visits every token, records its
-// covering range and copies the tokens whose sources are all literal bytes
-// (or lie before the window); later rounds visit the previous round's
-// leftovers.  A token copied in round r marks done = r; a token is ready in
-// round r only if its covering tokens are marked < r, i.e. were copied by an
-// earlier launch, so no access within a round races.
-template <bool FIRST>
-__global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
-  __shared__ FillStage stage[kCopyThreads / 64];
-  __shared__ uint32_t sub_end[kSub];  // inclusive prefix of the input sublist lengths
+// Level-synchronous rounds.  A token copied in round r marks done = r; a
+// token is ready in round r only if its covering tokens are marked < r, i.e.
+// were copied by an earlier launch, so no access within a round races.
+//
+// Round 0 runs one workgroup per window block.  It loads the block's output
+// (the literals the parse placed) into an LDS tile, finds each token's
+// covering range, fills the tokens whose sources are all literal bytes (or
+// lie before the window) into the tile, reading the sources from global
+// memory where they are final, and writes the tile back with 16-byte stores:
+// the match bytes of most tokens reach memory as whole lines instead of
+// byte-granular scattered writes.  Tokens of at least kSplitToken bytes go to
+// k_long.  Leftovers go to sublist (t / 64) mod kSub, so a sublist holds at
+// most ceil(T / 64 / kSub) * 64 tokens.
+__global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t tile[kMaxB];
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-  const uint32_t lane = lane_id();
-  FillStage& fs = stage[threadIdx.x >> 6];
+  const uint32_t lane = lane_id(), item = blockIdx.x;
   if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
-  uint32_t n_items = a.n_tok;
-  if (!FIRST) {
-    if (threadIdx.x < 64) {
-      uint32_t tot;
-      const uint32_t c = a.cnt_in[threadIdx.x * kCounterStride];
-      sub_end[threadIdx.x] = wave_excl_sum(c, &tot) + c;
-    }
-    __syncthreads();
-    n_items = sub_end[kSub - 1];
-  }
-  const uint32_t my_sub = blockIdx.x % kSub;
-  for (uint64_t base = uint64_t(blockIdx.x) * kCopyThreads; base < n_items; base += uint64_t(gridDim.x) * kCopyThreads) {
-    const uint64_t item = base + threadIdx.x;
-    const bool act = item < n_items;
-    uint32_t t = 0;
-    if (act) {
-      if (FIRST) {
-        t = uint32_t(item);
-      } else {  // sublist holding item
-        uint32_t sl = 0;
-#pragma unroll
-        for (uint32_t step = 32; step; step >>= 1)
-          if (sub_end[sl + step - 1] <= item) sl += step;
-        const uint32_t start = sub_end[sl] - (sl ? sub_end[sl] - sub_end[sl - 1] : sub_end[0]);
-        t = a.list_in[uint64_t(sl) * a.sub_cap + (item - start)];
-      }
-    }
+  const WinBlock wb = a.wbl[item];
+  const JobDev& J = a.jobs[wb.job];
+  const gbytes out = gp(J.out);
+  const uint32_t B = J.B;
+  const uint64_t bs = wb.b * B;
+  const uint32_t blen = uint32_t(min<uint64_t>(B, J.n_bytes - bs));
+  const uint32_t full = blen & ~15u;
+  for (uint32_t k = 16 * threadIdx.x; k < full; k += 16 * kCopyThreads)
+    *reinterpret_cast<u32x4*>(tile + k) = *reinterpret_cast<const AX_GLOBAL u32x4*>(out + bs + k);
+  for (uint32_t k = full + threadIdx.x; k < blen; k += kCopyThreads) tile[k] = out[bs + k];
+  __syncthreads();
+  const uint32_t t1 = item + 1 < a.n_items ? a.wbl[item + 1].tok : a.n_tok;
+  for (uint32_t base = wb.tok; base < t1; base += kCopyThreads) {
+    const uint32_t t = base + threadIdx.x;
+    const bool act = t < t1;
     uint64_t src = 0, dst = 0;
     uint32_t len = 0, lo = 0, cnt = 0;
-    gbytes out = nullptr;
     if (act) {
       token_at(a.tok, t, src, dst, len);
-      const WinBlock wb = a.wbl[a.tblk[t]];
-      const JobDev& J = a.jobs[wb.job];
-      out = gp(J.out);
-      if (FIRST) {
-        const uint64_t dist = dst - src;
-        find_cover(a, wb, J.B, src, src + (dist < len ? dist : len), lo, cnt);
-        a.cov[2 * t] = lo;
-        a.cov[2 * t + 1] = cnt;
-      } else {
-        lo = a.cov[2 * t];
-        cnt = a.cov[2 * t + 1];
-      }
+      const uint64_t dist = dst - src;
+      find_cover(a, wb, B, src, src + (dist < len ? dist : len), lo, cnt);
+      a.cov[2 * t] = lo;
+      a.cov[2 * t + 1] = cnt;
     }
-    bool ready = act;
-    for (uint32_t i = 0; i < cnt && ready; ++i) ready = a.done[lo + i] < a.round;
-    // round 0: long ready tokens are handed to k_long (a workgroup each) so
-    // that no wave carries a block-sized fill alone
-    const bool split = FIRST && ready && !a.serial && len >= kSplitToken;
+    const bool ready = act && cnt == 0;
+    const bool split = ready && !a.serial && len >= kSplitToken;
     const uint64_t sm = __ballot(split);
     if (sm) {
       uint32_t at = 0;
@@ -992,21 +972,117 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
       at = __shfl(at, 0, 64);
       if (split) a.long_list[at + lanes_below(sm)] = t;
     }
-    fill_ready<false>(out, ready && !split, dst, src, len, a.serial, FIRST ? a.fill_round : a.fill_tail, fs);
-    if (ready && !split) a.done[t] = uint8_t(a.round);
+    // tile fill: out[dst + k] = out[src + (k mod dist)], destination in the tile
+    const bool mine = ready && !split && (a.serial || len < kLongToken);
+    const uint32_t drel = uint32_t(dst - bs);
+    if (mine && a.serial) {  // the ablation: byte after byte, in-block sources read back from the tile
+      for (uint32_t k = 0; k < len; ++k) {
+        const uint64_t p = src + k;
+        tile[drel + k] = p < bs ? out[p] : tile[p - bs];
+      }
+    } else if (mine) {
+      const uint64_t dist = dst - src;
+      uint64_t j = 0;
+      for (uint32_t k0 = 0; k0 < len; k0 += 16) {
+        uint64_t idx[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          idx[q] = j;
+          if (++j == dist) j = 0;
+        }
+        uint8_t v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = (k0 + q < len) ? out[src + idx[q]] : uint8_t(0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (k0 + q < len) tile[drel + k0 + q] = v[q];
+      }
+    }
+    uint64_t wm = __ballot(ready && !split && !mine);  // medium tokens: the whole wave each
+    while (wm) {
+      const int l = __builtin_ctzll(wm);
+      wm &= wm - 1;
+      const uint64_t s0 = __shfl((unsigned long long)src, l, 64);
+      const uint32_t d0 = __shfl(drel, l, 64), n0 = __shfl(len, l, 64);
+      const uint64_t dist = bs + d0 - s0;
+      const uint32_t dd = dist < n0 ? uint32_t(dist) : n0;  // k < n0 <= dd: no wrap
+      for (uint32_t k = lane; k < n0; k += 64) tile[d0 + k] = out[s0 + (k % dd)];
+    }
+    if (ready && !split) a.done[t] = 0;
     const bool left = act && !ready;
-    const uint64_t m = __ballot(left);
-    if (FIRST) {
-      // round 0: a wave holds 64 consecutive tokens (64-aligned), so it owns
-      // two bitmap words; it writes its leftovers there when this round is
-      // the last, else clears them for the last round's marks
-      if ((lane & 31) == 0 && act) a.pbits[t >> 5] = a.mark ? uint32_t(m >> (lane & 32)) : 0u;
-      if (a.mark) continue;
-    } else if (a.mark) {
+    if (a.mark) {  // the only round: mark the leftovers for the persistent launch
       if (left) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
       continue;
     }
-    if (m) {  // leftovers go to this workgroup's sublist (counters spread over kSub addresses)
+    // a wave's tokens fall in at most two 64-token groups, hence two sublists
+    const uint32_t g0 = (base + (threadIdx.x & ~63u)) >> 6;
+#pragma unroll
+    for (uint32_t h = 0; h < 2; ++h) {
+      const uint64_t m = __ballot(left && (t >> 6) == g0 + h);
+      if (!m) continue;
+      const uint32_t sub = (g0 + h) % kSub, first = __builtin_ctzll(m);
+      uint32_t at = 0;
+      if (lane == first) at = atomicAdd(a.cnt_out + sub * kCounterStride, uint32_t(__popcll(m)));
+      at = __shfl(at, first, 64);
+      if (left && (t >> 6) == g0 + h) a.list_out[uint64_t(sub) * a.sub_cap + at + lanes_below(m)] = t;
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = 16 * threadIdx.x; k < full; k += 16 * kCopyThreads)
+    *reinterpret_cast<AX_GLOBAL u32x4*>(out + bs + k) = *reinterpret_cast<const u32x4*>(tile + k);
+  for (uint32_t k = full + threadIdx.x; k < blen; k += kCopyThreads) out[bs + k] = tile[k];
+}
+
+// Later rounds visit the previous round's leftovers.  Leftovers go to this
+// workgroup's sublist (counters spread over kSub addresses), or, in the last
+// round, to the bitmap of the persistent launch.
+__global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
+  __shared__ FillStage stage[kCopyThreads / 64];
+  __shared__ uint32_t sub_end[kSub];  // inclusive prefix of the input sublist lengths
+  if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  const uint32_t lane = lane_id();
+  FillStage& fs = stage[threadIdx.x >> 6];
+  if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
+  if (threadIdx.x < 64) {
+    uint32_t tot;
+    const uint32_t c = a.cnt_in[threadIdx.x * kCounterStride];
+    sub_end[threadIdx.x] = wave_excl_sum(c, &tot) + c;
+  }
+  __syncthreads();
+  const uint32_t n_items = sub_end[kSub - 1];
+  const uint32_t my_sub = blockIdx.x % kSub;
+  for (uint64_t base = uint64_t(blockIdx.x) * kCopyThreads; base < n_items; base += uint64_t(gridDim.x) * kCopyThreads) {
+    const uint64_t item = base + threadIdx.x;
+    const bool act = item < n_items;
+    uint32_t t = 0;
+    if (act) {  // sublist holding item
+      uint32_t sl = 0;
+#pragma unroll
+      for (uint32_t step = 32; step; step >>= 1)
+        if (sub_end[sl + step - 1] <= item) sl += step;
+      const uint32_t start = sub_end[sl] - (sl ? sub_end[sl] - sub_end[sl - 1] : sub_end[0]);
+      t = a.list_in[uint64_t(sl) * a.sub_cap + (item - start)];
+    }
+    uint64_t src = 0, dst = 0;
+    uint32_t len = 0, lo = 0, cnt = 0;
+    gbytes out = nullptr;
+    if (act) {
+      token_at(a.tok, t, src, dst, len);
+      out = token_out(a, t);
+      lo = a.cov[2 * t];
+      cnt = a.cov[2 * t + 1];
+    }
+    bool ready = act;
+    for (uint32_t i = 0; i < cnt && ready; ++i) ready = a.done[lo + i] < a.round;
+    fill_ready<false>(out, ready, dst, src, len, a.serial, a.fill_tail, fs);
+    if (ready) a.done[t] = uint8_t(a.round);
+    const bool left = act && !ready;
+    if (a.mark) {
+      if (left) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+      continue;
+    }
+    const uint64_t m = __ballot(left);
+    if (m) {
       uint32_t at = 0;
       if (lane == 0) at = atomicAdd(a.cnt_out + my_sub * kCounterStride, uint32_t(__popcll(m)));
       at = __shfl(at, 0, 64);
@@ -1183,7 +1259,7 @@ __global__ void k_window_init(DevStatus* st) {
 }
 
 __global__ void k_clear_u32(uint32_t* p, uint32_t n) {
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // --------------------------------------------------------------- host side --
@@ -1615,7 +1691,9 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
                   P->opt.bulk_rounds <= 1, 1ull << 22, copy_mode == AX_COPY_SERIAL, P->opt.fill_round,
                   P->opt.fill_tail, uint32_t(P->opt.tail_chunks)};
       const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
-      hipLaunchKernelGGL(k_round<true>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
+      const uint32_t n_words = (ntok + 31) / 32, pgrid = (n_words + kPackWords - 1) / kPackWords;
+      hipLaunchKernelGGL(k_clear_u32, dim3(pgrid), dim3(256), 0, s, ca.pbits, n_words);  // leftover bitmap
+      hipLaunchKernelGGL(k_round0, dim3(W.items), dim3(kCopyThreads), 0, s, ca);
       hipLaunchKernelGGL(k_long, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
       for (int r = 1; r < P->opt.bulk_rounds; ++r) {
         ca.round = uint32_t(r);
@@ -1626,10 +1704,9 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
         ca.cnt_clear = cset(r + 1);
         ca.mark = r + 1 == P->opt.bulk_rounds;
         // later rounds see the previous round's leftovers only
-        hipLaunchKernelGGL(k_round<false>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
+        hipLaunchKernelGGL(k_round, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       }
       ca.round = uint32_t(P->opt.bulk_rounds);
-      const uint32_t n_words = (ntok + 31) / 32, pgrid = (n_words + kPackWords - 1) / kPackWords;
       uint32_t* pcnt = reinterpret_cast<uint32_t*>(w + L.pcnt);
       hipLaunchKernelGGL(k_pcount, dim3(pgrid), dim3(kCopyThreads), 0, s, ca.pbits, n_words, pcnt);
       hipLaunchKernelGGL(k_pscatter, dim3(pgrid), dim3(kCopyThreads), 0, s, ca.pbits, n_words, pcnt,
