@@ -136,11 +136,10 @@ __device__ inline uint32_t wave_excl_sum(uint32_t v, uint32_t* total) {
 }
 
 __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
-  __shared__ uint8_t symtab[ax::kProbScale];
+  __shared__ __attribute__((aligned(16))) uint8_t symtab[ax::kProbScale];
   __shared__ uint32_t fctab[256];     // f | cum << 16, indexed by symbol
   __shared__ uint16_t cumtab[257];    // cum of the k-th present symbol, sentinel 4096
   __shared__ uint8_t symlist[256];    // k-th present symbol
-  __shared__ __attribute__((aligned(16))) uint8_t obuf[16 * 64];  // 16 steps of output, flushed as 16-byte stores
 
   const uint32_t item = blockIdx.x % a.n_items;
   const uint32_t stream = blockIdx.x / a.n_items;  // 0 LIT, 1 LEN, 2 OFF, 3 CMD
@@ -250,13 +249,20 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
       if (cumtab[mid] <= s0) lo = mid; else hi = mid - 1;
     }
     uint32_t k = lo, next = cumtab[k + 1];
-    for (uint32_t s = s0; s < s0 + 64; s += 4) {
-      uint32_t packed = 0;
-      for (uint32_t q = 0; q < 4; ++q) {
-        while (s + q >= next) { ++k; next = cumtab[k + 1]; }
-        packed |= uint32_t(symlist[k]) << (8 * q);
+    if (next >= s0 + 64) {  // one symbol owns all 64 slots: four 16-byte stores
+      const uint32_t rep = uint32_t(symlist[k]) * 0x01010101u;
+      const u32x4 v = {rep, rep, rep, rep};
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) *reinterpret_cast<u32x4*>(symtab + s0 + 16 * q) = v;
+    } else {
+      for (uint32_t s = s0; s < s0 + 64; s += 4) {
+        uint32_t packed = 0;
+        for (uint32_t q = 0; q < 4; ++q) {
+          while (s + q >= next) { ++k; next = cumtab[k + 1]; }
+          packed |= uint32_t(symlist[k]) << (8 * q);
+        }
+        *reinterpret_cast<uint32_t*>(symtab + s) = packed;
       }
-      *reinterpret_cast<uint32_t*>(symtab + s) = packed;
     }
   }
   __syncthreads();
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
     const uint32_t w = q < 64 ? va : vb;
     if (act) {
       x = need ? ((xn << 16) | w) : xn;
-      obuf[(t & 15) * K + lane] = uint8_t(s);
+      out[i] = uint8_t(s);
     }
     ptr += __popcll(m);
     if (ptr - base >= 64) {
@@ -292,17 +298,6 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
       wa = w1;
       w1 = w2;
       w2 = fetch(base + 128 + lane);
-    }
-    if ((t & 15) == 15 || t + 1 == steps) {
-      // symbols of steps t0..t are output bytes [t0*K, (t+1)*K): contiguous
-      // in obuf; 16-byte groups may run up to 15 bytes past n, which stays
-      // inside the slot (capacities are multiples of 16)
-      __syncthreads();
-      const uint32_t t0 = t & ~15u, have = min((t - t0 + 1) * K, n - t0 * K);
-      if (16 * lane < have)
-        *reinterpret_cast<AX_GLOBAL u32x4*>(out + t0 * K + 16 * lane) =
-            *reinterpret_cast<const u32x4*>(obuf + 16 * lane);
-      __syncthreads();
     }
   }
   bad |= lane < K && x != ax::kRansLow;
