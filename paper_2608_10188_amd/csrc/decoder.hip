@@ -349,10 +349,12 @@ __device__ inline uint64_t pick4(const uint64_t h[4], uint64_t j) {
 }
 
 struct ParseShared {
-  uint8_t tile[kMaxB];
-  uint32_t runbits[kMaxB / 32];   // run starts in the chunk's literal space
+  __attribute__((aligned(16))) uint8_t tile[kMaxB];
+  uint32_t runbits[kMaxB / 32];   // starts of the chunk's literal runs, in the block's output positions
   uint16_t runpre[kMaxB / 32];    // run starts in earlier words
-  uint16_t rundelta[kParseThreads];
+  uint16_t rundelta[kParseThreads];  // per run: output position - literal index
+  uint16_t runbeg[kParseThreads];    // per run: first output position
+  uint16_t runend[kParseThreads];    // per run: one past its last output position
   uint8_t offb[kOffStage];        // the block's decoded offset stream, when it fits
   uint8_t lenb[kLenStage];        // the block's decoded length stream, when it fits
   uint64_t offval[kParseThreads];
@@ -500,7 +502,7 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
   const uint32_t n_lit = a.nsym[4 * item + 0], n_len = a.nsym[4 * item + 1];
   const uint32_t n_off = a.nsym[4 * item + 2], n_cmd = a.nsym[4 * item + 3];
   const uint8_t* cmd = a.cmd + uint64_t(item) * a.slot_b;
-  const uint8_t* lit = a.lit + uint64_t(item) * a.slot_b;
+  const AX_GLOBAL uint8_t* const litg = gp(a.lit + uint64_t(item) * a.slot_b);
   const uint8_t* offs = a.off + uint64_t(item) * a.off_cap;
   const uint8_t* lens = a.len + uint64_t(item) * a.len_cap;
   const uint64_t* mpre = reinterpret_cast<const uint64_t*>(J.arc + 64) + J.nb + 1;
@@ -617,47 +619,66 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
         bad = true;
       }
     }
-    // literal runs: starts in the chunk's literal space
+    // literal runs: starts in the block's output positions
     for (uint32_t w = t; w < B / 32; w += kParseThreads) sh.runbits[w] = 0;
     __syncthreads();
     if (is0 && !bad && len) {
-      const uint32_t j = clit - litp;
-      atomicOr(&sh.runbits[j >> 5], 1u << (j & 31));
+      atomicOr(&sh.runbits[cdst >> 5], 1u << (cdst & 31));
       sh.rundelta[run_i] = uint16_t(cdst - clit);
+      sh.runbeg[run_i] = uint16_t(cdst);
+      sh.runend[run_i] = uint16_t(cdst + len);
     }
     if (__syncthreads_or(bad)) { failed = true; break; }
-    {  // run starts before each word of the chunk's literal space
-      const uint32_t nwords = (chunk_lit + 31) / 32;
+    const uint32_t n_runs = uint32_t((ctot >> 32) & 0xFFFF);
+    {  // run starts before each word of the output positions
       uint32_t c2[2] = {0, 0};
       for (uint32_t q = 0; q < 2; ++q) {
         const uint32_t w = 2 * t + q;
-        c2[q] = w < nwords ? __popc(sh.runbits[w]) : 0;
+        c2[q] = w < B / 32 ? __popc(sh.runbits[w]) : 0;
       }
       uint64_t rt;
       const uint64_t pre = block_excl_sum64(c2[0] + c2[1], &rt, sh, 0);
-      if (2 * t < nwords) sh.runpre[2 * t] = uint16_t(pre);
-      if (2 * t + 1 < nwords) sh.runpre[2 * t + 1] = uint16_t(pre + c2[0]);
+      if (2 * t < B / 32) sh.runpre[2 * t] = uint16_t(pre);
+      if (2 * t + 1 < B / 32) sh.runpre[2 * t + 1] = uint16_t(pre + c2[0]);
     }
     __syncthreads();
-    // place the chunk's literal bytes: aligned 16-byte groups of the literal
-    // stream, each byte moved by its run's (output - literal index) delta; a
-    // group finds its first byte's run once and steps to the next run at
-    // each run start inside the group
-    for (uint32_t g = (litp >> 4) + t; g < ((litp + chunk_lit + 15) >> 4); g += kParseThreads) {
-      const uint4 q = *reinterpret_cast<const uint4*>(lit + 16 * g);
-      const uint32_t word[4] = {q.x, q.y, q.z, q.w};
-      const uint32_t lo = max(16 * g, litp), hi = min(16 * g + 16, litp + chunk_lit);
-      const uint32_t j0 = lo - litp, w0 = j0 >> 5;
-      const uint32_t wa = sh.runbits[w0], wb = w0 + 1 < kMaxB / 32 ? sh.runbits[w0 + 1] : 0u;
-      const uint32_t starts = __builtin_amdgcn_alignbit(wb, wa, j0 & 31);  // bit k: literal j0 + k starts a run
-      uint32_t r = sh.runpre[w0] + __popc(wa & (0xFFFFFFFFu >> (31 - (j0 & 31)))) - 1;
-      uint32_t delta = sh.rundelta[r];
-#pragma unroll
-      for (uint32_t k = 0; k < 16; ++k) {
-        const uint32_t li = 16 * g + k;
-        if (li < lo || li >= hi) continue;
-        if (li > lo && ((starts >> (li - lo)) & 1u)) delta = sh.rundelta[++r];
-        sh.tile[li + delta] = uint8_t(word[k >> 2] >> (8 * (k & 3)));
+    // place the chunk's literal bytes by aligned 16-byte output groups: each
+    // literal run meeting a group supplies 16 consecutive literal bytes (two
+    // aligned loads shifted into place) under the group's byte mask, and the
+    // group is merged into the tile with one 16-byte read and write (bytes
+    // outside the runs keep their value)
+    const uint32_t dend = dst + uint32_t(ptot & 0xFFFFFFFFu);
+    for (uint32_t c = (dst >> 4) + t; 16 * c < dend; c += kParseThreads) {
+      const uint32_t d0 = max(16 * c, dst), d1 = min(16 * c + 16, dend), w = d0 >> 5;
+      int32_t r = int32_t(sh.runpre[w] + __popc(sh.runbits[w] & (0xFFFFFFFFu >> (31 - (d0 & 31))))) - 1;
+      if (r < 0 || d0 >= sh.runend[r]) ++r;  // the run holding d0, else the next one
+      u32x4 val = {0, 0, 0, 0}, msk = {0, 0, 0, 0};
+      for (; r < int32_t(n_runs) && sh.runbeg[r] < d1; ++r) {
+        const uint32_t x0 = max(d0, uint32_t(sh.runbeg[r])), x1 = min(d1, uint32_t(sh.runend[r]));
+        const int32_t l0 = int32_t(16 * c) - int32_t(sh.rundelta[r]);  // literal index of the group's byte 0
+        const int32_t al = l0 & ~15;                                    // may be -16: still inside the workspace
+        const u32x4 lo4 = *reinterpret_cast<const AX_GLOBAL u32x4*>(litg + al);
+        const u32x4 hi4 = *reinterpret_cast<const AX_GLOBAL u32x4*>(litg + al + 16);
+        const uint32_t sb = uint32_t(l0 - al), rb = sb & 3;
+        const bool q2 = sb & 8, q1 = sb & 4;
+        // the 32 loaded bytes shifted down by sb: first by whole dwords (two
+        // selects), then by rb bytes across dword pairs
+        const uint32_t t0 = q2 ? lo4.z : lo4.x, t1 = q2 ? lo4.w : lo4.y, t2 = q2 ? hi4.x : lo4.z;
+        const uint32_t t3 = q2 ? hi4.y : lo4.w, t4 = q2 ? hi4.z : hi4.x, t5 = q2 ? hi4.w : hi4.y;
+        const uint32_t u0 = q1 ? t1 : t0, u1 = q1 ? t2 : t1, u2 = q1 ? t3 : t2, u3 = q1 ? t4 : t3,
+                       u4 = q1 ? t5 : t4;
+        const u32x4 e = {__builtin_amdgcn_alignbyte(u1, u0, rb), __builtin_amdgcn_alignbyte(u2, u1, rb),
+                         __builtin_amdgcn_alignbyte(u3, u2, rb), __builtin_amdgcn_alignbyte(u4, u3, rb)};
+        const uint32_t m16 = ((1u << (x1 - 16 * c)) - 1u) & ~((1u << (x0 - 16 * c)) - 1u);
+        const u32x4 nib = {m16 & 15u, (m16 >> 4) & 15u, (m16 >> 8) & 15u, (m16 >> 12) & 15u};
+        const u32x4 bm = ((nib * 0x00204081u) & 0x01010101u) * 0xFFu;
+        val = (val & ~bm) | (e & bm);
+        msk |= bm;
+        if (sh.runend[r] >= d1) break;
+      }
+      if (msk.x | msk.y | msk.z | msk.w) {
+        u32x4& cell = *reinterpret_cast<u32x4*>(sh.tile + 16 * c);
+        cell = (cell & ~msk) | val;
       }
     }
     __syncthreads();
