@@ -476,7 +476,7 @@ def main():
                    "ratio": round(n / c_bytes, 4), "blocks": int(dec.info.n_blocks),
                    "commands": int(st.n_commands), "matches": int(st.n_matches), "repeats": int(st.n_rep),
                    "copy_mode": args.copy, "no_rep": bool(args.no_rep), "depth_cap": args.depth_cap,
-                   "max_depth": int(st.max_depth) if args.depth_cap else None, "bulk_rounds": args.bulk_rounds or 4, "fill": args.fill or "1,0", "tail_chunks": args.tail_chunks or 1},
+                   "max_depth": int(st.max_depth) if args.depth_cap else None, "bulk_rounds": args.bulk_rounds or 4, "fill": args.fill or "0,0", "tail_chunks": args.tail_chunks or 1},
         "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 5),
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         "stage_share": {k: round(v / max(1e-9, sum(stages.values())), 4) for k, v in stages.items()},

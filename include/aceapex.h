@@ -165,10 +165,11 @@ int aceapex_decoder_set_timing(aceapex_decoder* dec, int enable);
  *     finishes the deeper tokens, in [1, 250] (default 4). */
 enum { AX_OPT_BULK_ROUNDS = 1 };
 /*   AX_OPT_FILL_ROUNDS / AX_OPT_FILL_TAIL  how a wave fills its ready tokens
- *     in the first round / in the later rounds and the persistent launch:
- *     0 short tokens one lane each and long ones by the whole wave, 1 all
- *     ready tokens laid end to end and split evenly over the lanes
- *     (defaults 1 / 0). */
+ *     in the rounds after the first / in the persistent launch: 0 short
+ *     tokens one lane each and long ones by the whole wave, 1 all ready
+ *     tokens laid end to end and split evenly over the lanes (defaults 0 / 0).
+ *     AX_OPT_FILL_ROUNDS also applies to the first round when it runs as
+ *     waves (AX_OPT_ROUND0_TILE = 0). */
 enum { AX_OPT_FILL_ROUNDS = 2, AX_OPT_FILL_TAIL = 3 };
 /*   AX_OPT_TAIL_CHUNKS  consecutive 64-token chunks a wave of the persistent
  *     launch takes per ticket, in [1, 64] (default 1): fewer tickets (one
@@ -178,6 +179,11 @@ enum { AX_OPT_FILL_ROUNDS = 2, AX_OPT_FILL_TAIL = 3 };
  *     replay it afterwards (re-captured when the workspace, copy mode or an
  *     option changes); stage timing is not recorded in this mode. */
 enum { AX_OPT_TAIL_CHUNKS = 4, AX_OPT_GRAPH = 5 };
+/*   AX_OPT_ROUND0_TILE  schedule of the first match-layer round: 1 = one
+ *     workgroup per block, filling its tokens in a 16 KiB LDS tile written
+ *     back as 16-byte stores (default); 0 = one wave per 64 tokens writing
+ *     the fills straight to global memory (fill mode AX_OPT_FILL_ROUNDS). */
+enum { AX_OPT_ROUND0_TILE = 6 };
 int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
 
 /* Read the device status word of a workspace after the work queued on

@@ -28,7 +28,7 @@ EXPORTS = [
     "aceapex_decoder_build_index", "aceapex_closure_blocks", "aceapex_range_plan_create", "aceapex_range_plan_destroy",
     "aceapex_range_plan_workspace", "aceapex_range_plan_last", "aceapex_decode_ranges", "aceapex_decode_range",
 ]
-OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH = 1, 2, 3, 4, 5
+OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH, OPT_ROUND0_TILE = 1, 2, 3, 4, 5, 6
 
 
 class AceapexError(RuntimeError):

@@ -726,7 +726,7 @@ struct CopyArgs {
   int mark;                  // this round is the last: mark leftovers in pbits
   uint64_t spin_limit;
   int serial;
-  int fill_round, fill_tail;  // kFillLaneWave or kFillSegmented
+  int fill_round, fill_tail;  // later rounds / persistent launch: kFillLaneWave or kFillSegmented
   uint32_t tail_chunks;       // consecutive 64-token chunks per persistent-launch ticket
 };
 
@@ -1049,6 +1049,61 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   for (uint32_t k = full + threadIdx.x; k < blen; k += kCopyThreads) out[bs + k] = tile[k];
 }
 
+// Round 0 as a flat grid over the window's tokens (the alternative
+// schedule): 64 consecutive tokens per wave, fills written straight to
+// global memory by the wave (short tokens a lane each, long ones the wave,
+// or all laid end to end over the lanes).  Same results and lists as
+// k_round0; the leftovers of a wave (64-aligned tokens) fall in one 64-token
+// group and so in one sublist.
+__global__ __launch_bounds__(kCopyThreads) void k_round0_waves(CopyArgs a) {
+  __shared__ FillStage stage[kCopyThreads / 64];
+  if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  const uint32_t lane = lane_id();
+  FillStage& fs = stage[threadIdx.x >> 6];
+  if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
+  for (uint64_t base = uint64_t(blockIdx.x) * kCopyThreads; base < a.n_tok; base += uint64_t(gridDim.x) * kCopyThreads) {
+    const uint32_t t = uint32_t(base + threadIdx.x);
+    const bool act = t < a.n_tok;
+    uint64_t src = 0, dst = 0;
+    uint32_t len = 0, lo = 0, cnt = 0;
+    gbytes out = nullptr;
+    if (act) {
+      token_at(a.tok, t, src, dst, len);
+      const WinBlock wb = a.wbl[a.tblk[t]];
+      const JobDev& J = a.jobs[wb.job];
+      out = gp(J.out);
+      const uint64_t dist = dst - src;
+      find_cover(a, wb, J.B, src, src + (dist < len ? dist : len), lo, cnt);
+      a.cov[2 * t] = lo;
+      a.cov[2 * t + 1] = cnt;
+    }
+    const bool ready = act && cnt == 0;
+    const bool split = ready && !a.serial && len >= kSplitToken;
+    const uint64_t sm = __ballot(split);
+    if (sm) {
+      uint32_t at = 0;
+      if (lane == 0) at = atomicAdd(a.long_cnt, uint32_t(__popcll(sm)));
+      at = __shfl(at, 0, 64);
+      if (split) a.long_list[at + lanes_below(sm)] = t;
+    }
+    fill_ready<false>(out, ready && !split, dst, src, len, a.serial, a.fill_round, fs);
+    if (ready && !split) a.done[t] = 0;
+    const bool left = act && !ready;
+    if (a.mark) {
+      if (left) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+      continue;
+    }
+    const uint64_t m = __ballot(left);
+    if (m) {
+      const uint32_t sub = (t >> 6) % kSub;  // the same for the whole wave
+      uint32_t at = 0;
+      if (lane == 0) at = atomicAdd(a.cnt_out + sub * kCounterStride, uint32_t(__popcll(m)));
+      at = __shfl(at, 0, 64);
+      if (left) a.list_out[uint64_t(sub) * a.sub_cap + at + lanes_below(m)] = t;
+    }
+  }
+}
+
 // Later rounds visit the previous round's leftovers.  Leftovers go to this
 // workgroup's sublist (counters spread over kSub addresses), or, in the last
 // round, to the bitmap of the persistent launch.
@@ -1090,7 +1145,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     }
     bool ready = act;
     for (uint32_t i = 0; i < cnt && ready; ++i) ready = a.done[lo + i] < a.round;
-    fill_ready<false>(out, ready, dst, src, len, a.serial, a.fill_tail, fs);
+    fill_ready<false>(out, ready, dst, src, len, a.serial, a.fill_round, fs);
     if (ready) a.done[t] = uint8_t(a.round);
     const bool left = act && !ready;
     if (a.mark) {
@@ -1621,6 +1676,10 @@ int plan_set_option(Plan* P, int option, int64_t value) {
       if (value < 1 || value > 64) return fail(AX_E_ARG, "tail chunks must be in [1, 64]");
       P->opt.tail_chunks = int(value);
       break;
+    case AX_OPT_ROUND0_TILE:
+      if (value < 0 || value > 1) return fail(AX_E_ARG, "round-0 schedule must be 0 or 1");
+      P->opt.round0_tile = int(value);
+      break;
     case AX_OPT_FILL_ROUNDS:
     case AX_OPT_FILL_TAIL:
       if (value < 0 || value > 1) return fail(AX_E_ARG, "fill mode must be 0 or 1");
@@ -1644,6 +1703,7 @@ int plan_get_option(const Plan* P, int option, int64_t* value) {
   switch (option) {
     case AX_OPT_BULK_ROUNDS: *value = P->opt.bulk_rounds; return AX_OK;
     case AX_OPT_TAIL_CHUNKS: *value = P->opt.tail_chunks; return AX_OK;
+    case AX_OPT_ROUND0_TILE: *value = P->opt.round0_tile; return AX_OK;
     case AX_OPT_FILL_ROUNDS: *value = P->opt.fill_round; return AX_OK;
     case AX_OPT_FILL_TAIL: *value = P->opt.fill_tail; return AX_OK;
     case AX_OPT_GRAPH: *value = P->opt.graph; return AX_OK;
@@ -1709,7 +1769,8 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
       const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
       const uint32_t n_words = (ntok + 31) / 32, pgrid = (n_words + kPackWords - 1) / kPackWords;
       hipLaunchKernelGGL(k_clear_u32, dim3(pgrid), dim3(256), 0, s, ca.pbits, n_words);  // leftover bitmap
-      hipLaunchKernelGGL(k_round0, dim3(W.items), dim3(kCopyThreads), 0, s, ca);
+      if (P->opt.round0_tile) hipLaunchKernelGGL(k_round0, dim3(W.items), dim3(kCopyThreads), 0, s, ca);
+      else hipLaunchKernelGGL(k_round0_waves, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       hipLaunchKernelGGL(k_long, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
       for (int r = 1; r < P->opt.bulk_rounds; ++r) {
         ca.round = uint32_t(r);

@@ -15,9 +15,10 @@ struct Plan;
 // Schedule knobs of a plan; none changes a decoded byte.
 struct PlanOptions {
   int bulk_rounds = 4;  // level-synchronous match-layer rounds before the persistent launch
-  int fill_round = 1;   // round 0: segmented fill
-  int fill_tail = 0;    // later rounds and persistent launch: lane/wave fill
+  int fill_round = 0;   // rounds after the first: lane/wave fill
+  int fill_tail = 0;    // persistent launch: lane/wave fill
   int tail_chunks = 1;  // 64-token chunks per persistent-launch ticket
+  int round0_tile = 1;  // round 0: a workgroup per block through an LDS tile (1) or a wave per 64 tokens (0)
   int graph = 0;        // replay the launch sequence from a captured hipGraph
 };
 
