@@ -1314,23 +1314,23 @@ __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
   }
 }
 
-__global__ void k_init(DevStatus* st) {
-  if (threadIdx.x == 0) {
-    st->err = 0;
-    st->bad_block = ~0ull;
-  }
+// Zero two word ranges (one launch for both).
+__global__ void k_clear2(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) q[i] = 0;
 }
 
-__global__ void k_window_init(DevStatus* st) {
+// Status reset before each window (the first also clears the error word).
+__global__ void k_window_init(DevStatus* st, int first) {
   if (threadIdx.x == 0) {
+    if (first) {
+      st->err = 0;
+      st->bad_block = ~0ull;
+    }
     st->ticket = 0;
     st->long_count = 0;
     st->n_pending = 0;
   }
-}
-
-__global__ void k_clear_u32(uint32_t* p, uint32_t n) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // --------------------------------------------------------------- host side --
@@ -1618,10 +1618,10 @@ int plan_parse_tokens(Plan* P, void* d_work, uint64_t work_len, hipStream_t s, u
     for (size_t j = 0; j < P->jobs.size(); ++j) P->dev_out[j] = P->jobs[j].out;
   }
   std::vector<uint64_t> tk;
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, st);
+  if (P->wins.empty()) hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st, 1);  // status only
   for (const Plan::Win& W : P->wins) {
     const WinBlock* wbl = P->d_wbl + W.at;
-    hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st, int(&W == &P->wins.front()));
     AnsArgs aa{P->d_jobs, wbl, W.items, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                P->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
     hipLaunchKernelGGL(k_ans, dim3(4 * W.items), dim3(64), 0, s, aa);
@@ -1737,12 +1737,13 @@ int plan_stage_ms(Plan* P, float* ans, float* parse, float* copy) {
 static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool timed) {
   const Layout& L = P->lay;
   DevStatus* st = reinterpret_cast<DevStatus*>(w + L.status);
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, st);
+  if (P->wins.empty()) hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st, 1);  // status only
   for (size_t wi = 0; wi < P->wins.size(); ++wi) {
     const Plan::Win& W = P->wins[wi];
     const bool first = wi == 0, last = wi + 1 == P->wins.size();
     const WinBlock* wbl = P->d_wbl + W.at;
-    hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st, int(first));
+    uint32_t* counts = reinterpret_cast<uint32_t*>(w + L.counts);
     AnsArgs aa{P->d_jobs, wbl, W.items, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                P->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
     if (timed && first) (void)hipEventRecord(P->ev[0], s);
@@ -1756,9 +1757,11 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
     const uint32_t ntok = W.tok;
     if (ntok) {
       uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(w + L.list0), reinterpret_cast<uint32_t*>(w + L.list1)};
-      uint32_t* counts = reinterpret_cast<uint32_t*>(w + L.counts);
       auto cset = [&](int r) { return counts + (r % 3) * kSub * kCounterStride; };
-      hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(256), 0, s, counts, uint32_t(3 * kSub * kCounterStride));
+      const uint32_t n_words = (ntok + 31) / 32, pgrid = (n_words + kPackWords - 1) / kPackWords;
+      // the list counters and the leftover bitmap start at zero
+      hipLaunchKernelGGL(k_clear2, dim3(pgrid), dim3(256), 0, s, counts, uint32_t(3 * kSub * kCounterStride),
+                         reinterpret_cast<uint32_t*>(w + L.pbits), n_words);
       CopyArgs ca{P->d_jobs, wbl, W.items, reinterpret_cast<const uint64_t*>(w + L.tok),
                   reinterpret_cast<const uint32_t*>(w + L.tblk), ntok, reinterpret_cast<uint32_t*>(w + L.cov),
                   w + L.done, nullptr, lists[0], nullptr, cset(0), cset(1), uint32_t(L.sub_cap),
@@ -1767,8 +1770,6 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
                   P->opt.bulk_rounds <= 1, 1ull << 22, copy_mode == AX_COPY_SERIAL, P->opt.fill_round,
                   P->opt.fill_tail, uint32_t(P->opt.tail_chunks)};
       const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
-      const uint32_t n_words = (ntok + 31) / 32, pgrid = (n_words + kPackWords - 1) / kPackWords;
-      hipLaunchKernelGGL(k_clear_u32, dim3(pgrid), dim3(256), 0, s, ca.pbits, n_words);  // leftover bitmap
       if (P->opt.round0_tile) hipLaunchKernelGGL(k_round0, dim3(W.items), dim3(kCopyThreads), 0, s, ca);
       else hipLaunchKernelGGL(k_round0_waves, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       hipLaunchKernelGGL(k_long, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);

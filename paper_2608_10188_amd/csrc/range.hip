@@ -24,40 +24,71 @@
 
 namespace {
 
-// Merged set of disjoint half-open intervals.
-class IntervalSet {
+// Byte-precise set of needed output positions: one bitmap per touched block
+// (B bits), allocated from a pool.  Inserting a range reports the runs of
+// positions that were not needed before, which become new work.
+class NeedSet {
  public:
-  // Insert [a, b); append to `added` the parts that were not present.
-  void insert(uint64_t a, uint64_t b, std::vector<std::pair<uint64_t, uint64_t>>& added) {
-    if (a >= b) return;
-    auto it = m_.upper_bound(a);
-    if (it != m_.begin()) {
-      auto p = std::prev(it);
-      if (p->second >= a) it = p;
+  explicit NeedSet(uint64_t B) : B_(B), words_(B / 64) {}
+
+  // Mark [a, b) needed; append to `fresh` the maximal runs newly marked.
+  void insert(uint64_t a, uint64_t b, std::vector<std::pair<uint64_t, uint64_t>>& fresh) {
+    uint64_t run0 = 0;
+    bool open = false;
+    while (a < b) {
+      const uint64_t blk = a / B_, base = blk * B_, e = std::min(b, base + B_);
+      uint64_t* bm = bitmap(blk);
+      for (uint64_t p = a; p < e;) {
+        const uint64_t w = (p - base) >> 6, bit = (p - base) & 63;
+        const uint64_t n = std::min<uint64_t>(64 - bit, e - p);
+        const uint64_t m = (n == 64 ? ~0ull : ((1ull << n) - 1)) << bit;
+        uint64_t nw = m & ~bm[w];
+        bm[w] |= m;
+        // walk the word's bits [bit, bit + n): runs of newly marked positions
+        uint64_t q = bit;
+        while (q < bit + n) {
+          const bool isnew = (nw >> q) & 1;
+          const uint64_t rest = isnew ? ~nw : nw;  // first position where the state flips
+          uint64_t flip = rest >> q ? q + __builtin_ctzll(rest >> q) : 64;
+          flip = std::min<uint64_t>(flip, bit + n);
+          const uint64_t pa = base + w * 64 + q;
+          if (isnew && !open) run0 = pa, open = true;
+          if (!isnew && open) fresh.emplace_back(run0, pa), open = false;
+          q = flip;
+        }
+        p += n;
+      }
+      a = e;
     }
-    uint64_t cur = a, lo = a, hi = b;
-    while (it != m_.end() && it->first <= b) {
-      if (it->first > cur) added.emplace_back(cur, it->first);
-      cur = std::max(cur, it->second);
-      lo = std::min(lo, it->first);
-      hi = std::max(hi, it->second);
-      it = m_.erase(it);
-    }
-    if (cur < b) added.emplace_back(cur, b);
-    m_.emplace(lo, hi);
+    if (open) fresh.emplace_back(run0, b);
   }
-  const std::map<uint64_t, uint64_t>& items() const { return m_; }
+
+  // Ascending list of touched blocks.
+  void blocks(std::vector<uint64_t>& out) const {
+    for (const auto& kv : slot_) out.push_back(kv.first);
+  }
 
  private:
-  std::map<uint64_t, uint64_t> m_;
+  uint64_t* bitmap(uint64_t blk) {
+    auto it = slot_.find(blk);
+    if (it == slot_.end()) {
+      it = slot_.emplace(blk, pool_.size()).first;
+      pool_.resize(pool_.size() + words_, 0);
+    }
+    return pool_.data() + it->second;
+  }
+  uint64_t B_, words_;
+  std::map<uint64_t, size_t> slot_;
+  std::vector<uint64_t> pool_;
 };
 
-// Closure of one range: needed intervals, from the highest position down.
-void closure_of(const aceapex_decoder* d, uint64_t off, uint64_t len, IntervalSet& need) {
+// Closure of one range: every position whose byte the range's bytes depend
+// on, found by following each needed match byte to its source.
+void closure_of(const aceapex_decoder* d, uint64_t off, uint64_t len, NeedSet& need) {
   const uint64_t B = d->info.block_size;
   const auto& src = d->idx_src;
   const auto& dl = d->idx_dstlen;
-  std::vector<std::pair<uint64_t, uint64_t>> work, added;
+  std::vector<std::pair<uint64_t, uint64_t>> work;
   need.insert(off, off + len, work);
   while (!work.empty()) {
     const auto iv = work.back();
@@ -77,24 +108,16 @@ void closure_of(const aceapex_decoder* d, uint64_t off, uint64_t len, IntervalSe
         if (dst >= iv.second) break;
         const uint64_t k0 = std::max(iv.first, dst) - dst, k1 = std::min(iv.second, dst + n) - dst;
         const uint64_t dist = dst - src[t];
-        added.clear();
         if (k1 - k0 >= dist) {
-          need.insert(src[t], src[t] + std::min(n, dist), added);
+          need.insert(src[t], src[t] + std::min(n, dist), work);
         } else {
           const uint64_t a = k0 % dist, b = a + (k1 - k0);
-          if (b <= dist) need.insert(src[t] + a, src[t] + b, added);
-          else need.insert(src[t] + a, src[t] + dist, added), need.insert(src[t], src[t] + (b - dist), added);
+          if (b <= dist) need.insert(src[t] + a, src[t] + b, work);
+          else need.insert(src[t] + a, src[t] + dist, work), need.insert(src[t], src[t] + (b - dist), work);
         }
-        for (auto& p : added) work.push_back(p);
       }
     }
   }
-}
-
-void blocks_of(const IntervalSet& need, uint64_t B, std::vector<uint64_t>& out) {
-  for (const auto& iv : need.items())
-    for (uint64_t b = iv.first / B; b <= (iv.second - 1) / B; ++b)
-      if (out.empty() || out.back() != b) out.push_back(b);
 }
 
 // Closures of many ranges in parallel, merged into one ascending block list.
@@ -112,9 +135,9 @@ int union_closure(const aceapex_decoder* d, uint32_t n, const uint64_t* offs, co
       const uint32_t i = next.fetch_add(1);
       if (i >= n) break;
       if (!lens[i]) continue;
-      IntervalSet need;
+      NeedSet need(d->info.block_size);
       closure_of(d, offs[i], lens[i], need);
-      blocks_of(need, d->info.block_size, part[w]);
+      need.blocks(part[w]);
     }
   };
   std::vector<std::thread> pool;
