@@ -937,23 +937,36 @@ __device__ inline void fill_ready(gbytes out, bool ready, uint64_t dst, uint64_t
   __builtin_amdgcn_wave_barrier();
 }
 
+// Workgroup g of a grid of n is dispatched to XCD g mod 8 (round-robin);
+// this gives every XCD a contiguous run of items instead, so neighbouring
+// blocks share an L2 (a block's match sources are mostly just behind it).
+__device__ inline uint32_t xcd_item(uint32_t g, uint32_t n) {
+  const uint32_t x = g & 7u, slot = g >> 3, q = n >> 3, r = n & 7u;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
+}
+
 // Level-synchronous rounds.  A token copied in round r marks done = r; a
 // token is ready in round r only if its covering tokens are marked < r, i.e.
 // were copied by an earlier launch, so no access within a round races.
 //
-// Round 0 runs one workgroup per window block.  It loads the block's output
-// (the literals the parse placed) into an LDS tile, finds each token's
-// covering range, fills the tokens whose sources are all literal bytes (or
-// lie before the window) into the tile, reading the sources from global
-// memory where they are final, and writes the tile back with 16-byte stores:
-// the match bytes of most tokens reach memory as whole lines instead of
-// byte-granular scattered writes.  Tokens of at least kSplitToken bytes go to
-// k_long.  Leftovers go to sublist (t / 64) mod kSub, so a sublist holds at
-// most ceil(T / 64 / kSub) * 64 tokens.
+// Round 0 runs one workgroup per window block, in four passes.  (1) Each
+// token's covering range is found; ready tokens (sources all literal bytes,
+// or before the window) are noted in LDS with the 16-byte chunks of the block
+// they will write, leftovers go to the next round's lists.  (2) Those chunks
+// of the block's output (the literals the parse placed) are loaded into an
+// LDS tile.  (3) The ready tokens are filled into the tile, sources read from
+// global memory where they are final.  (4) The chunks are written back with
+// 16-byte stores: the match bytes reach memory as whole chunks instead of
+// byte-granular scattered writes, and chunks without match bytes are neither
+// read nor written.  Tokens of at least kSplitToken bytes go to k_long.
+// Leftovers go to sublist (t / 64) mod kSub, so a sublist holds at most
+// ceil(T / 64 / kSub) * 64 tokens.
 __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t tile[kMaxB];
+  __shared__ uint32_t dirty[kMaxB / 16 / 32];  // chunks of the tile that receive match bytes
+  __shared__ uint32_t rdy[kMaxB / 32];         // the block's tokens filled here (min_match >= 1)
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-  const uint32_t lane = lane_id(), item = blockIdx.x;
+  const uint32_t lane = lane_id(), item = xcd_item(blockIdx.x, gridDim.x);
   if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
   const WinBlock wb = a.wbl[item];
   const JobDev& J = a.jobs[wb.job];
@@ -961,12 +974,13 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   const uint32_t B = J.B;
   const uint64_t bs = wb.b * B;
   const uint32_t blen = uint32_t(min<uint64_t>(B, J.n_bytes - bs));
-  const uint32_t full = blen & ~15u;
-  for (uint32_t k = 16 * threadIdx.x; k < full; k += 16 * kCopyThreads)
-    *reinterpret_cast<u32x4*>(tile + k) = *reinterpret_cast<const AX_GLOBAL u32x4*>(out + bs + k);
-  for (uint32_t k = full + threadIdx.x; k < blen; k += kCopyThreads) tile[k] = out[bs + k];
-  __syncthreads();
+  const uint32_t nchunk = (blen + 15) / 16;
   const uint32_t t1 = item + 1 < a.n_items ? a.wbl[item + 1].tok : a.n_tok;
+  const uint32_t ntb = t1 - wb.tok;  // <= blen: tokens are at least a byte long
+  // the serial ablation reads in-block sources back from the tile: load all of it
+  for (uint32_t k = threadIdx.x; k < kMaxB / 16 / 32; k += kCopyThreads) dirty[k] = a.serial ? ~0u : 0u;
+  for (uint32_t k = threadIdx.x; k < (ntb + 31) / 32; k += kCopyThreads) rdy[k] = 0;
+  __syncthreads();
   for (uint32_t base = wb.tok; base < t1; base += kCopyThreads) {
     const uint32_t t = base + threadIdx.x;
     const bool act = t < t1;
@@ -988,8 +1002,55 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       at = __shfl(at, 0, 64);
       if (split) a.long_list[at + lanes_below(sm)] = t;
     }
+    if (ready && !split) {
+      a.done[t] = 0;
+      const uint32_t r = t - wb.tok, drel = uint32_t(dst - bs);
+      atomicOr(&rdy[r >> 5], 1u << (r & 31));
+      const uint32_t c0 = drel >> 4, c1 = (drel + len - 1) >> 4;  // len < kSplitToken: a few words
+      for (uint32_t w = c0 >> 5; w <= c1 >> 5; ++w) {
+        const uint32_t lo_b = w == (c0 >> 5) ? (c0 & 31) : 0, hi_b = w == (c1 >> 5) ? (c1 & 31) : 31;
+        atomicOr(&dirty[w], (hi_b == 31 ? ~0u : (2u << hi_b) - 1) & ~((1u << lo_b) - 1));
+      }
+    }
+    const bool left = act && !ready;
+    if (a.mark) {  // the only round: mark the leftovers for the persistent launch
+      if (left) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+      continue;
+    }
+    // a wave's tokens fall in at most two 64-token groups, hence two sublists
+    const uint32_t g0 = (base + (threadIdx.x & ~63u)) >> 6;
+#pragma unroll
+    for (uint32_t h = 0; h < 2; ++h) {
+      const uint64_t m = __ballot(left && (t >> 6) == g0 + h);
+      if (!m) continue;
+      const uint32_t sub = (g0 + h) % kSub, first = __builtin_ctzll(m);
+      uint32_t at = 0;
+      if (lane == first) at = atomicAdd(a.cnt_out + sub * kCounterStride, uint32_t(__popcll(m)));
+      at = __shfl(at, first, 64);
+      if (left && (t >> 6) == g0 + h) a.list_out[uint64_t(sub) * a.sub_cap + at + lanes_below(m)] = t;
+    }
+  }
+  __syncthreads();
+  const uint32_t full = blen / 16;
+  for (uint32_t k = threadIdx.x; k < nchunk; k += kCopyThreads) {
+    if (!((dirty[k >> 5] >> (k & 31)) & 1)) continue;
+    if (k < full) {
+      *reinterpret_cast<u32x4*>(tile + 16 * k) = *reinterpret_cast<const AX_GLOBAL u32x4*>(out + bs + 16 * k);
+    } else {
+      for (uint32_t i = 16 * k; i < blen; ++i) tile[i] = out[bs + i];
+    }
+  }
+  __syncthreads();
+  for (uint32_t base = wb.tok; base < t1; base += kCopyThreads) {
+    const uint32_t t = base + threadIdx.x;
+    const uint32_t r = t - wb.tok;
+    const bool ready = t < t1 && ((rdy[r >> 5] >> (r & 31)) & 1);
+    if (!__ballot(ready)) continue;
+    uint64_t src = 0, dst = 0;
+    uint32_t len = 0;
+    if (ready) token_at(a.tok, t, src, dst, len);
     // tile fill: out[dst + k] = out[src + (k mod dist)], destination in the tile
-    const bool mine = ready && !split && (a.serial || len < kLongToken);
+    const bool mine = ready && (a.serial || len < kLongToken);
     const uint32_t drel = uint32_t(dst - bs);
     if (mine && a.serial) {  // the ablation: byte after byte, in-block sources read back from the tile
       for (uint32_t k = 0; k < len; ++k) {
@@ -1014,7 +1075,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
           if (k0 + q < len) tile[drel + k0 + q] = v[q];
       }
     }
-    uint64_t wm = __ballot(ready && !split && !mine);  // medium tokens: the whole wave each
+    uint64_t wm = __ballot(ready && !mine);  // medium tokens: the whole wave each
     while (wm) {
       const int l = __builtin_ctzll(wm);
       wm &= wm - 1;
@@ -1024,29 +1085,16 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       const uint32_t dd = dist < n0 ? uint32_t(dist) : n0;  // k < n0 <= dd: no wrap
       for (uint32_t k = lane; k < n0; k += 64) tile[d0 + k] = out[s0 + (k % dd)];
     }
-    if (ready && !split) a.done[t] = 0;
-    const bool left = act && !ready;
-    if (a.mark) {  // the only round: mark the leftovers for the persistent launch
-      if (left) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
-      continue;
-    }
-    // a wave's tokens fall in at most two 64-token groups, hence two sublists
-    const uint32_t g0 = (base + (threadIdx.x & ~63u)) >> 6;
-#pragma unroll
-    for (uint32_t h = 0; h < 2; ++h) {
-      const uint64_t m = __ballot(left && (t >> 6) == g0 + h);
-      if (!m) continue;
-      const uint32_t sub = (g0 + h) % kSub, first = __builtin_ctzll(m);
-      uint32_t at = 0;
-      if (lane == first) at = atomicAdd(a.cnt_out + sub * kCounterStride, uint32_t(__popcll(m)));
-      at = __shfl(at, first, 64);
-      if (left && (t >> 6) == g0 + h) a.list_out[uint64_t(sub) * a.sub_cap + at + lanes_below(m)] = t;
-    }
   }
   __syncthreads();
-  for (uint32_t k = 16 * threadIdx.x; k < full; k += 16 * kCopyThreads)
-    *reinterpret_cast<AX_GLOBAL u32x4*>(out + bs + k) = *reinterpret_cast<const u32x4*>(tile + k);
-  for (uint32_t k = full + threadIdx.x; k < blen; k += kCopyThreads) out[bs + k] = tile[k];
+  for (uint32_t k = threadIdx.x; k < nchunk; k += kCopyThreads) {
+    if (!((dirty[k >> 5] >> (k & 31)) & 1)) continue;
+    if (k < full) {
+      *reinterpret_cast<AX_GLOBAL u32x4*>(out + bs + 16 * k) = *reinterpret_cast<const u32x4*>(tile + 16 * k);
+    } else {
+      for (uint32_t i = 16 * k; i < blen; ++i) out[bs + i] = tile[i];
+    }
+  }
 }
 
 // Round 0 as a flat grid over the window's tokens (the alternative
