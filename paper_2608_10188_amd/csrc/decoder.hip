@@ -391,17 +391,46 @@ struct ParseShared {
   int32_t wlast[4];
   uint32_t leb_found, leb_cursor;
   int bad;
+  alignas(4) uint8_t anyb[2][4];  // block_any: one byte per wave, two call sites
 };
 
-// Block-wide exclusive scan of a u64 (sum), 256 threads.
+// Block-wide "any thread's p" (256 threads): a ballot per wave, one LDS byte
+// per wave, one barrier.  Slot k's bytes are rewritten only after a later
+// barrier, so every thread has read them.
+__device__ inline bool block_any(bool p, ParseShared& sh, int k) {
+  const bool w = __ballot(p) != 0;
+  if (lane_id() == 0) sh.anyb[k][threadIdx.x >> 6] = uint8_t(w);
+  __syncthreads();
+  return *reinterpret_cast<const uint32_t*>(sh.anyb[k]) != 0;
+}
+
+// Wave-level moves for the scans (DPP): row_shr:k moves each lane's value k
+// lanes up inside its row of 16; row_bcast:15 / :31 hand lane 15 / 31 to the
+// rows selected by the row mask.  Lanes without a source, or in unselected
+// rows, receive `id`.
+constexpr int kDppRowShr = 0x110, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp_move(uint32_t id, uint32_t x) {
+  return uint32_t(__builtin_amdgcn_update_dpp(int(id), int(x), CTRL, ROWS, 0xF, false));
+}
+
+// Inclusive wave scan of a u32 (sum): 1, 2, 4, 8 inside the rows, then the
+// row totals across rows.
+__device__ inline uint32_t wave_incl_sum32(uint32_t x) {
+  x += dpp_move<kDppRowShr + 1, 0xF>(0, x);
+  x += dpp_move<kDppRowShr + 2, 0xF>(0, x);
+  x += dpp_move<kDppRowShr + 4, 0xF>(0, x);
+  x += dpp_move<kDppRowShr + 8, 0xF>(0, x);
+  x += dpp_move<kDppRowBcast15, 0xA>(0, x);
+  x += dpp_move<kDppRowBcast31, 0xC>(0, x);
+  return x;
+}
+
+// Block-wide exclusive scan of a u64 holding two u32 sums (the halves are
+// scanned separately: no half may carry), 256 threads.
 __device__ inline uint64_t block_excl_sum64(uint64_t v, uint64_t* total, ParseShared& sh, int slotk) {
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  uint64_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint64_t y = __shfl_up((unsigned long long)x, o, 64);
-    if (lane >= (uint32_t)o) x += y;
-  }
+  const uint64_t x = wave_incl_sum32(uint32_t(v)) | (uint64_t(wave_incl_sum32(uint32_t(v >> 32))) << 32);
   if (lane == 63) sh.wsum[wv][slotk] = x;
   __syncthreads();
   uint64_t pre = 0, tot = 0;
@@ -417,17 +446,19 @@ __device__ inline uint64_t block_excl_sum64(uint64_t v, uint64_t* total, ParseSh
 
 // Block-wide exclusive scan of history maps; returns the map before this
 // command and the chunk's total map.
-__device__ inline HMap map_shfl_up(HMap m, int o) {
-  return HMap{uint32_t(__shfl_up(int(m.v), o, 64)), uint32_t(__shfl_up(int(m.t), o, 64))};
+template <int CTRL, int ROWS>
+__device__ inline HMap map_dpp(HMap m) {
+  return HMap{dpp_move<CTRL, ROWS>(kMapId.v, m.v), dpp_move<CTRL, ROWS>(kMapId.t, m.t)};
 }
 __device__ inline HMap block_excl_map(HMap m, HMap* total, ParseShared& sh) {
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  HMap x = m;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const HMap y = map_shfl_up(x, o);
-    if (lane >= (uint32_t)o) x = map_after(x, y);
-  }
+  HMap x = m;  // inclusive wave scan, earlier lanes' maps applied first (the identity fills gaps)
+  x = map_after(x, map_dpp<kDppRowShr + 1, 0xF>(x));
+  x = map_after(x, map_dpp<kDppRowShr + 2, 0xF>(x));
+  x = map_after(x, map_dpp<kDppRowShr + 4, 0xF>(x));
+  x = map_after(x, map_dpp<kDppRowShr + 8, 0xF>(x));
+  x = map_after(x, map_dpp<kDppRowBcast15, 0xA>(x));
+  x = map_after(x, map_dpp<kDppRowBcast31, 0xC>(x));
   if (lane == 63) sh.wmap[wv] = x;
   __syncthreads();
   HMap pre = kMapId, tot = kMapId;
@@ -437,8 +468,7 @@ __device__ inline HMap block_excl_map(HMap m, HMap* total, ParseShared& sh) {
   }
   __syncthreads();
   *total = tot;
-  const HMap incl_prev = map_shfl_up(x, 1);  // inclusive of the previous lane
-  return map_after(lane == 0 ? kMapId : incl_prev, pre);
+  return map_after(map_dpp<kDppWaveShr1, 0xF>(x), pre);  // inclusive of the previous lane
 }
 
 // Distance named by slot k of a map: an input slot of hist, or an explicit
@@ -508,7 +538,7 @@ __device__ bool leb_values(Src src, uint32_t n, uint32_t* cursor, uint32_t count
     win += 256;
     __syncthreads();
   }
-  if (__syncthreads_or(!ok)) return false;
+  if (block_any(!ok, sh, 0)) return false;
   if (count) *cursor = sh.leb_cursor;
   __syncthreads();
   return true;
@@ -652,7 +682,7 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
       sh.runbeg[run_i] = uint16_t(cdst);
       sh.runend[run_i] = uint16_t(cdst + len);
     }
-    if (__syncthreads_or(bad)) { failed = true; break; }
+    if (block_any(bad, sh, 1)) { failed = true; break; }
     const uint32_t n_runs = uint32_t((ctot >> 32) & 0xFFFF);
     {  // run starts before each word of the output positions
       uint32_t c2[2] = {0, 0};
