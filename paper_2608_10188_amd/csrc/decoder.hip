@@ -49,11 +49,12 @@ __device__ inline AX_GLOBAL T* gp(T* p) {
   return (AX_GLOBAL T*)p;
 }
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef u32x4 u32x4_u __attribute__((aligned(1)));  // 16 bytes at any byte address (one dwordx4 load)
 
 constexpr uint32_t kMaxB = 16384;           // largest block the device path decodes
 constexpr uint32_t kParseThreads = 256;
-constexpr uint32_t kOffStage = 4096;        // offset-stream bytes staged in LDS by k_parse
-constexpr uint32_t kLenStage = 1024;        // length-stream bytes staged in LDS by k_parse
+constexpr uint32_t kOffStage = 1792;        // offset-stream bytes staged in LDS by k_parse
+constexpr uint32_t kLenStage = 256;         // length-stream bytes staged in LDS by k_parse
 constexpr uint32_t kCopyThreads = 256;      // match-layer workgroup
 constexpr uint8_t kPending = 0xFF;          // done[] value of a token not yet copied
 constexpr uint32_t kSub = 64;               // pending-list sublists (one counter each, 256 B apart)
@@ -374,18 +375,20 @@ __device__ inline uint64_t pick4(const uint64_t h[4], uint64_t j) {
 
 struct ParseShared {
   __attribute__((aligned(16))) uint8_t tile[kMaxB];
-  uint32_t runbits[kMaxB / 32];   // starts of the chunk's literal runs, in the block's output positions
-  uint16_t runpre[kMaxB / 32];    // run starts in earlier words
+  uint64_t runbits[kMaxB / 64];   // starts of the chunk's literal runs, in the block's output positions
+  uint16_t runpre[kMaxB / 64];    // run starts in earlier words
   uint16_t rundelta[kParseThreads];  // per run: output position - literal index
   uint16_t runbeg[kParseThreads];    // per run: first output position
   uint16_t runend[kParseThreads];    // per run: one past its last output position
   uint8_t offb[kOffStage];        // the block's decoded offset stream, when it fits
   uint8_t lenb[kLenStage];        // the block's decoded length stream, when it fits
   uint64_t offval[kParseThreads];
-  uint32_t lenval[kParseThreads];
   uint64_t wsum[4][2];
   HMap wmap[4];
-  uint64_t cdist[kParseThreads];  // distance of the explicit match at each chunk position
+  union {
+    uint64_t cdist[kParseThreads];   // distance of the explicit match at each chunk position
+    uint32_t lenval[kParseThreads];  // length extensions: read before cdist is written (a barrier apart)
+  };
   uint64_t last4[4];              // the chunk's last explicit-match distances, newest first
   uint32_t wterm[4];
   int32_t wlast[4];
@@ -674,55 +677,41 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
       }
     }
     // literal runs: starts in the block's output positions
-    for (uint32_t w = t; w < B / 32; w += kParseThreads) sh.runbits[w] = 0;
+    for (uint32_t w = t; w < B / 64; w += kParseThreads) sh.runbits[w] = 0;
     __syncthreads();
     if (is0 && !bad && len) {
-      atomicOr(&sh.runbits[cdst >> 5], 1u << (cdst & 31));
+      atomicOr(reinterpret_cast<uint32_t*>(sh.runbits) + (cdst >> 5), 1u << (cdst & 31));
       sh.rundelta[run_i] = uint16_t(cdst - clit);
       sh.runbeg[run_i] = uint16_t(cdst);
       sh.runend[run_i] = uint16_t(cdst + len);
     }
     if (block_any(bad, sh, 1)) { failed = true; break; }
     const uint32_t n_runs = uint32_t((ctot >> 32) & 0xFFFF);
-    {  // run starts before each word of the output positions
-      uint32_t c2[2] = {0, 0};
-      for (uint32_t q = 0; q < 2; ++q) {
-        const uint32_t w = 2 * t + q;
-        c2[q] = w < B / 32 ? __popc(sh.runbits[w]) : 0;
-      }
+    {  // run starts before each word of the output positions (B / 64 <= 256 words)
+      const uint32_t c = t < B / 64 ? __popcll(sh.runbits[t]) : 0;
       uint64_t rt;
-      const uint64_t pre = block_excl_sum64(c2[0] + c2[1], &rt, sh, 0);
-      if (2 * t < B / 32) sh.runpre[2 * t] = uint16_t(pre);
-      if (2 * t + 1 < B / 32) sh.runpre[2 * t + 1] = uint16_t(pre + c2[0]);
+      const uint64_t pre = block_excl_sum64(c, &rt, sh, 0);
+      if (t < B / 64) sh.runpre[t] = uint16_t(pre);
     }
     __syncthreads();
     // place the chunk's literal bytes by aligned 16-byte output groups: each
-    // literal run meeting a group supplies 16 consecutive literal bytes (two
-    // aligned loads shifted into place) under the group's byte mask, and the
-    // group is merged into the tile with one 16-byte read and write (bytes
-    // outside the runs keep their value)
+    // literal run meeting a group supplies the 16 literal bytes lined up with
+    // the group under the group's byte mask, and the group is merged into the
+    // tile with one 16-byte read and write (bytes outside the runs keep their
+    // value)
     const uint32_t dend = dst + uint32_t(ptot & 0xFFFFFFFFu);
     for (uint32_t c = (dst >> 4) + t; 16 * c < dend; c += kParseThreads) {
-      const uint32_t d0 = max(16 * c, dst), d1 = min(16 * c + 16, dend), w = d0 >> 5;
-      int32_t r = int32_t(sh.runpre[w] + __popc(sh.runbits[w] & (0xFFFFFFFFu >> (31 - (d0 & 31))))) - 1;
+      const uint32_t d0 = max(16 * c, dst), d1 = min(16 * c + 16, dend), w = d0 >> 6;
+      int32_t r = int32_t(sh.runpre[w] + __popcll(sh.runbits[w] & (~0ull >> (63 - (d0 & 63))))) - 1;
       if (r < 0 || d0 >= sh.runend[r]) ++r;  // the run holding d0, else the next one
       u32x4 val = {0, 0, 0, 0}, msk = {0, 0, 0, 0};
       for (; r < int32_t(n_runs) && sh.runbeg[r] < d1; ++r) {
         const uint32_t x0 = max(d0, uint32_t(sh.runbeg[r])), x1 = min(d1, uint32_t(sh.runend[r]));
         const int32_t l0 = int32_t(16 * c) - int32_t(sh.rundelta[r]);  // literal index of the group's byte 0
-        const int32_t al = l0 & ~15;                                    // may be -16: still inside the workspace
-        const u32x4 lo4 = *reinterpret_cast<const AX_GLOBAL u32x4*>(litg + al);
-        const u32x4 hi4 = *reinterpret_cast<const AX_GLOBAL u32x4*>(litg + al + 16);
-        const uint32_t sb = uint32_t(l0 - al), rb = sb & 3;
-        const bool q2 = sb & 8, q1 = sb & 4;
-        // the 32 loaded bytes shifted down by sb: first by whole dwords (two
-        // selects), then by rb bytes across dword pairs
-        const uint32_t t0 = q2 ? lo4.z : lo4.x, t1 = q2 ? lo4.w : lo4.y, t2 = q2 ? hi4.x : lo4.z;
-        const uint32_t t3 = q2 ? hi4.y : lo4.w, t4 = q2 ? hi4.z : hi4.x, t5 = q2 ? hi4.w : hi4.y;
-        const uint32_t u0 = q1 ? t1 : t0, u1 = q1 ? t2 : t1, u2 = q1 ? t3 : t2, u3 = q1 ? t4 : t3,
-                       u4 = q1 ? t5 : t4;
-        const u32x4 e = {__builtin_amdgcn_alignbyte(u1, u0, rb), __builtin_amdgcn_alignbyte(u2, u1, rb),
-                         __builtin_amdgcn_alignbyte(u3, u2, rb), __builtin_amdgcn_alignbyte(u4, u3, rb)};
+        // the 16 literal bytes lined up with the group: one unaligned load
+        // (l0 may be as low as -15, and the load may run past the stream:
+        // still inside the workspace)
+        const u32x4 e = *reinterpret_cast<const AX_GLOBAL u32x4_u*>(litg + l0);
         const uint32_t m16 = ((1u << (x1 - 16 * c)) - 1u) & ~((1u << (x0 - 16 * c)) - 1u);
         const u32x4 nib = {m16 & 15u, (m16 >> 4) & 15u, (m16 >> 8) & 15u, (m16 >> 12) & 15u};
         const u32x4 bm = ((nib * 0x00204081u) & 0x01010101u) * 0xFFu;
