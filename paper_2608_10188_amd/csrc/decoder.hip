@@ -138,9 +138,11 @@ __device__ inline uint32_t wave_excl_sum(uint32_t v, uint32_t* total) {
 
 __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t symtab[ax::kProbScale];
-  __shared__ uint32_t fctab[256];     // f | cum << 16, indexed by symbol
-  __shared__ uint16_t cumtab[257];    // cum of the k-th present symbol, sentinel 4096
-  __shared__ uint8_t symlist[256];    // k-th present symbol
+  // f | cum << 16 indexed by symbol; while the slot table is filled, the same
+  // bytes hold the cum (sentinel 4096) and the symbol of the k-th present one
+  __shared__ __attribute__((aligned(16))) uint32_t fctab[256];
+  uint16_t* const cumtab = reinterpret_cast<uint16_t*>(fctab);         // 257 entries
+  uint8_t* const symlist = reinterpret_cast<uint8_t*>(fctab) + 2 * 260;  // 256 entries
 
   const uint32_t item = blockIdx.x % a.n_items;
   const uint32_t stream = blockIdx.x / a.n_items;  // 0 LIT, 1 LEN, 2 OFF, 3 CMD
@@ -234,11 +236,13 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
     if (lane == 0) { report(a.st, AX_E_CORRUPT, b); *nsym = 0; }
     return;
   }
-  for (uint32_t j = 0; j < cnt; ++j) {
-    fctab[mysym[j]] = myf[j] | (cum << 16);
-    cumtab[rank0 + j] = uint16_t(cum);
-    symlist[rank0 + j] = uint8_t(mysym[j]);
-    cum += myf[j];
+  {
+    uint32_t c = cum;
+    for (uint32_t j = 0; j < cnt; ++j) {
+      cumtab[rank0 + j] = uint16_t(c);
+      symlist[rank0 + j] = uint8_t(mysym[j]);
+      c += myf[j];
+    }
   }
   if (lane == 0) cumtab[present] = ax::kProbScale;
   __syncthreads();
@@ -265,6 +269,11 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
         *reinterpret_cast<uint32_t*>(symtab + s) = packed;
       }
     }
+  }
+  __syncthreads();
+  for (uint32_t j = 0; j < cnt; ++j) {  // now the frequency table (over the build's lists)
+    fctab[mysym[j]] = myf[j] | (cum << 16);
+    cum += myf[j];
   }
   __syncthreads();
   // --- decode: lane j owns symbols j, j+K, ...
