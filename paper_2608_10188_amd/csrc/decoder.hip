@@ -50,6 +50,7 @@ __device__ inline AX_GLOBAL T* gp(T* p) {
 }
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef u32x4 u32x4_u __attribute__((aligned(1)));  // 16 bytes at any byte address (one dwordx4 load)
+typedef u32x4 u32x4_u __attribute__((aligned(1)));  // 16 bytes at any byte address (one dwordx4 load)
 
 constexpr uint32_t kMaxB = 16384;           // largest block the device path decodes
 constexpr uint32_t kParseThreads = 256;
@@ -1113,6 +1114,14 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       const uint64_t dist = dst - src;
       uint64_t j = 0;
       for (uint32_t k0 = 0; k0 < len; k0 += 16) {
+        if (src + k0 + 16 <= dst) {  // 16 source bytes before the destination: one unaligned load
+          const u32x4 v = *reinterpret_cast<const AX_GLOBAL u32x4_u*>(out + src + k0);
+#pragma unroll
+          for (uint32_t q = 0; q < 16; ++q)
+            if (k0 + q < len) tile[drel + k0 + q] = uint8_t(v[q >> 2] >> (8 * (q & 3)));
+          j = k0 + 16 == dist ? 0 : k0 + 16;  // dist >= k0 + 16: the periodic index of the next byte
+          continue;
+        }
         uint64_t idx[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
