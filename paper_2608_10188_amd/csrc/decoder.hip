@@ -56,6 +56,7 @@ constexpr uint32_t kMaxB = 16384;           // largest block the device path dec
 constexpr uint32_t kParseThreads = 256;
 constexpr uint32_t kOffStage = 1792;        // offset-stream bytes staged in LDS by k_parse
 constexpr uint32_t kLenStage = 256;         // length-stream bytes staged in LDS by k_parse
+constexpr uint32_t kLenBpt = 1, kOffBpt = 2;  // LEB bytes per thread per pass: length / offset streams
 constexpr uint32_t kCopyThreads = 256;      // match-layer workgroup
 constexpr uint8_t kPending = 0xFF;          // done[] value of a token not yet copied
 constexpr uint32_t kSub = 64;               // pending-list sublists (one counter each, 256 B apart)
@@ -492,63 +493,75 @@ __device__ inline uint64_t map_value(HMap m, uint32_t k, const uint64_t hist[4],
 }
 
 // Decode `count` consecutive LEB128 values starting at byte *cursor of
-// src[0..n) into dst (u64) — all 256 threads. Returns false on a malformed
-// or missing value.  *cursor advances past the last value.
-template <class Src>
+// src[0..n) into dst (u64) — all 256 threads, BPT bytes each per window of
+// 256 * BPT.  A byte below 0x80 ends a value; terminators are counted by a block
+// scan, and each terminator's thread assembles its value from the bytes after
+// the previous terminator.  Returns false on a malformed or missing value.
+// *cursor advances past the last value.
+template <uint32_t BPT, class Src>
 __device__ bool leb_values(Src src, uint32_t n, uint32_t* cursor, uint32_t count, uint64_t* dst,
                            ParseShared& sh) {
   const uint32_t t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+  const uint32_t first = *cursor;
   uint32_t found = 0;
-  uint32_t win = *cursor;
-  uint32_t value_start = win;  // start of the value that is open at the window start
+  uint32_t win = first & ~(BPT - 1);
+  uint32_t value_start = first;  // start of the value that is open at the window start
   bool ok = true;
   while (found < count) {
     if (win >= n) { ok = false; break; }
-    const uint32_t pos = win + t;
-    const bool inb = pos < n;
-    const uint8_t byte = inb ? src[pos] : 0x80;
-    const bool term = inb && byte < 0x80;
-    const uint64_t m = __ballot(term);
-    const uint32_t before_in_wave = lanes_below(m);
-    const uint64_t lower = m & ((1ull << lane) - 1ull);
-    const int32_t prev_in_wave = lower ? int32_t(63 - __clzll(lower)) : -1;
-    if (lane == 0) {
-      sh.wterm[wv] = __popcll(m);
-      sh.wlast[wv] = m ? int32_t(63 - __clzll(m)) + int32_t(wv * 64) : -1;
+    const uint32_t p0 = win + BPT * t;
+    uint32_t tm = 0;  // terminators among this thread's bytes
+#pragma unroll
+    for (uint32_t q = 0; q < BPT; ++q) {
+      const uint32_t pos = p0 + q;
+      if (pos >= first && pos < n && src[pos] < 0x80) tm |= 1u << q;
     }
+    const uint32_t c = __popc(tm);
+    const uint32_t incl = wave_incl_sum32(c);
+    const int32_t mylast = tm ? int32_t(p0 + 31 - __clz(tm)) : -1;
+    const uint64_t hm = __ballot(tm != 0);
+    if (lane == 63) sh.wterm[wv] = incl;
+    if (hm == 0 ? lane == 0 : lane == uint32_t(63 - __clzll(hm))) sh.wlast[wv] = mylast;
     __syncthreads();
-    uint32_t before = before_in_wave, all = 0;
-    int32_t prev = prev_in_wave >= 0 ? prev_in_wave + int32_t(wv * 64) : -1;
+    uint32_t before = incl - c, all = 0;
     for (uint32_t k = 0; k < 4; ++k) {
       if (k < wv) before += sh.wterm[k];
       all += sh.wterm[k];
     }
+    // the last terminator before this thread's bytes
+    const uint64_t lower = hm & ((1ull << lane) - 1ull);
+    const int32_t from_lane = __shfl(mylast, lower ? 63 - __clzll(lower) : 0, 64);
+    int32_t prev = lower ? from_lane : -1;
     if (prev < 0)
       for (int32_t k = int32_t(wv) - 1; k >= 0; --k)
         if (sh.wlast[k] >= 0) { prev = sh.wlast[k]; break; }
-    if (term) {
-      const uint32_t vi = found + before;
-      const uint32_t start = prev >= 0 ? win + uint32_t(prev) + 1 : value_start;
+    uint32_t vi = found + before;
+    uint32_t start = prev >= 0 ? uint32_t(prev) + 1 : value_start;
+    for (uint32_t q = 0; q < BPT; ++q) {
+      if (!((tm >> q) & 1)) continue;
+      const uint32_t pos = p0 + q;
       if (vi < count) {
         if (pos + 1 - start > 10) {
           ok = false;
         } else {
           uint64_t v = 0;
-          for (uint32_t q = start; q <= pos; ++q) v |= uint64_t(src[q] & 0x7F) << (7 * (q - start));
+          for (uint32_t r = start; r <= pos; ++r) v |= uint64_t(src[r] & 0x7F) << (7 * (r - start));
           if (pos - start == 9 && src[pos] > 1) ok = false;
           dst[vi] = v;
           if (vi == count - 1) sh.leb_cursor = pos + 1;
         }
       }
+      ++vi;
+      start = pos + 1;
     }
     // the value still open at the end of this window starts after its last terminator
     int32_t last = -1;
     for (int32_t k = 3; k >= 0; --k)
       if (sh.wlast[k] >= 0) { last = sh.wlast[k]; break; }
-    if (last >= 0) value_start = win + uint32_t(last) + 1;
-    if (win + 256 - value_start > 10 && found + all < count) ok = false;  // a value longer than 10 bytes
+    if (last >= 0) value_start = uint32_t(last) + 1;
+    if (win + BPT * kParseThreads - value_start > 10 && found + all < count) ok = false;  // a value longer than 10 bytes
     found += all;
-    win += 256;
+    win += BPT * kParseThreads;
     __syncthreads();
   }
   if (block_any(!ok, sh, 0)) return false;
@@ -557,7 +570,8 @@ __device__ bool leb_values(Src src, uint32_t n, uint32_t* cursor, uint32_t count
   return true;
 }
 
-__global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
+// Six waves per SIMD (at most 80 VGPRs), as many as the LDS allows.
+__global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
   __shared__ ParseShared sh;
   const uint32_t item = blockIdx.x, t = threadIdx.x;
   const WinBlock wb = a.wbl[item];
@@ -614,8 +628,8 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
     const uint32_t n_tokc = uint32_t(ctot >> 48);
     // length and offset values of this chunk
     uint64_t* lv64 = sh.offval;  // reuse: lengths first, then offsets
-    if (!(len_lds ? leb_values(static_cast<const uint8_t*>(sh.lenb), n_len, &lenc, n_esc, lv64, sh)
-                  : leb_values(leng, n_len, &lenc, n_esc, lv64, sh))) {
+    if (!(len_lds ? leb_values<kLenBpt>(static_cast<const uint8_t*>(sh.lenb), n_len, &lenc, n_esc, lv64, sh)
+                  : leb_values<kLenBpt>(leng, n_len, &lenc, n_esc, lv64, sh))) {
       failed = true;
       break;
     }
@@ -624,8 +638,8 @@ __global__ __launch_bounds__(kParseThreads) void k_parse(ParseArgs a) {
       sh.lenval[t] = e > B ? 0xFFFFFFFFu : uint32_t(e);
     }
     __syncthreads();
-    if (!(off_lds ? leb_values(static_cast<const uint8_t*>(sh.offb), n_off, &offc, n_k1, sh.offval, sh)
-                  : leb_values(offg, n_off, &offc, n_k1, sh.offval, sh))) {
+    if (!(off_lds ? leb_values<kOffBpt>(static_cast<const uint8_t*>(sh.offb), n_off, &offc, n_k1, sh.offval, sh)
+                  : leb_values<kOffBpt>(offg, n_off, &offc, n_k1, sh.offval, sh))) {
       failed = true;
       break;
     }
