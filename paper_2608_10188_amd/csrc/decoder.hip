@@ -737,8 +737,13 @@ __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
         // still inside the workspace)
         const u32x4 e = *reinterpret_cast<const AX_GLOBAL u32x4_u*>(litg + l0);
         const uint32_t m16 = ((1u << (x1 - 16 * c)) - 1u) & ~((1u << (x0 - 16 * c)) - 1u);
+        // byte i of the group's mask is 0xFF when bit i of m16 is set: each
+        // nibble spread to one bit per byte, then a byte permute whose
+        // selector 12 gives 0x00 and 13 gives 0xFF (no 32-bit multiply)
         const u32x4 nib = {m16 & 15u, (m16 >> 4) & 15u, (m16 >> 8) & 15u, (m16 >> 12) & 15u};
-        const u32x4 bm = ((nib * 0x00204081u) & 0x01010101u) * 0xFFu;
+        const u32x4 sel = ((nib * 0x00204081u) & 0x01010101u) | 0x0C0C0C0Cu;
+        const u32x4 bm = {__builtin_amdgcn_perm(0u, 0u, sel.x), __builtin_amdgcn_perm(0u, 0u, sel.y),
+                          __builtin_amdgcn_perm(0u, 0u, sel.z), __builtin_amdgcn_perm(0u, 0u, sel.w)};
         val = (val & ~bm) | (e & bm);
         msk |= bm;
         if (sh.runend[r] >= d1) break;
