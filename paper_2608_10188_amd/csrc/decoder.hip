@@ -897,8 +897,8 @@ __device__ inline void fill_lane(gbytes out, uint64_t dst, uint64_t src, uint32_
 template <bool COH>
 __device__ inline void fill_wave(gbytes out, uint64_t dst, uint64_t src, uint32_t len, uint32_t lane) {
   const uint64_t dist = dst - src;
-  const uint64_t step = 64 % dist;
-  uint64_t j = lane % dist;
+  const uint64_t step = dist > 64 ? 64 : 64 % uint32_t(dist);  // no 64-bit division
+  uint64_t j = dist > lane ? lane : lane % uint32_t(dist);
   for (uint32_t k0 = lane; k0 < len; k0 += 512) {
     uint64_t idx[8];
 #pragma unroll
@@ -1162,8 +1162,14 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       const uint64_t s0 = __shfl((unsigned long long)src, l, 64);
       const uint32_t d0 = __shfl(drel, l, 64), n0 = __shfl(len, l, 64);
       const uint64_t dist = bs + d0 - s0;
-      const uint32_t dd = dist < n0 ? uint32_t(dist) : n0;  // k < n0 <= dd: no wrap
-      for (uint32_t k = lane; k < n0; k += 64) tile[d0 + k] = out[s0 + (k % dd)];
+      const uint32_t dd = dist < n0 ? uint32_t(dist) : n0;  // the period (n0 when it never wraps)
+      const uint32_t step = 64 % dd;
+      uint32_t j = lane % dd;
+      for (uint32_t k = lane; k < n0; k += 64) {
+        tile[d0 + k] = out[s0 + j];
+        j += step;
+        if (j >= dd) j -= dd;
+      }
     }
   }
   __syncthreads();
@@ -1303,8 +1309,8 @@ __global__ __launch_bounds__(kCopyThreads) void k_long(CopyArgs a) {
     token_at(a.tok, t, src, dst, len);
     const gbytes out = token_out(a, t);
     const uint64_t dist = dst - src;
-    const uint64_t step = uint64_t(kCopyThreads) % dist;
-    uint64_t j = threadIdx.x % dist;
+    const uint64_t step = dist > kCopyThreads ? kCopyThreads : kCopyThreads % uint32_t(dist);
+    uint64_t j = dist > threadIdx.x ? threadIdx.x : threadIdx.x % uint32_t(dist);
     for (uint32_t k0 = threadIdx.x; k0 < len; k0 += 16 * kCopyThreads) {
       uint64_t idx[16];
 #pragma unroll
