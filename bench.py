@@ -79,6 +79,7 @@ def parse_args():
     ap.add_argument("--bulk-rounds", type=int, default=0, help="level-synchronous copy rounds (0 = library default)")
     ap.add_argument("--tail-chunks", type=int, default=0, help="chunks per persistent-launch ticket (0 = default)")
     ap.add_argument("--fill", default="", help="fill modes 'R,T' for rounds and tail (0 lane/wave, 1 segmented)")
+    ap.add_argument("--graph", type=int, default=0, help="1: each decode replays the plan captured as one hipGraph")
     return ap.parse_args()
 
 
@@ -386,6 +387,8 @@ def main():
         fr, ft = (int(v) for v in args.fill.split(","))
         dec.set_option(ax.OPT_FILL_ROUNDS, fr)
         dec.set_option(ax.OPT_FILL_TAIL, ft)
+    if args.graph:
+        dec.set_option(ax.OPT_GRAPH, 1)
     stream = torch.cuda.current_stream()
     if args.calib_copy_mib:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE under a
@@ -477,7 +480,8 @@ def main():
                    "ratio": round(n / c_bytes, 4), "blocks": int(dec.info.n_blocks),
                    "commands": int(st.n_commands), "matches": int(st.n_matches), "repeats": int(st.n_rep),
                    "copy_mode": args.copy, "no_rep": bool(args.no_rep), "depth_cap": args.depth_cap,
-                   "max_depth": int(st.max_depth) if args.depth_cap else None, "bulk_rounds": args.bulk_rounds or 4, "fill": args.fill or "0,0", "tail_chunks": args.tail_chunks or 1},
+                   "max_depth": int(st.max_depth) if args.depth_cap else None, "bulk_rounds": args.bulk_rounds or 4, "fill": args.fill or "0,0", "tail_chunks": args.tail_chunks or 1,
+                   "graph": bool(args.graph)},
         "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 5),
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         "stage_share": {k: round(v / max(1e-9, sum(stages.values())), 4) for k, v in stages.items()},
