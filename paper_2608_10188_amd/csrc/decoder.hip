@@ -8,18 +8,21 @@
 //            ballot + prefix count over a register window of the word stream.
 //   k_parse  one workgroup per block: commands are parsed 256 at a time by
 //            block-wide prefix scans (positions, literal positions, value
-//            indices) and an associative scan of the four-entry distance
-//            history (each command is a map on history tuples); literal runs
-//            are placed into an LDS tile that is written out with 16-byte
-//            stores; matches become tokens (src, dst, len).
+//            indices; DPP moves inside the wave) and an associative scan of
+//            the four-entry distance history (each command is a map on
+//            history tuples); literal runs are placed into an LDS tile that
+//            is written out with 16-byte stores; matches become tokens
+//            (src, dst, len).
 //   match layer: every token (src, dst, len) is written as a periodic fill
 //            out[dst+k] = out[src + k mod dist] (periodic-fill section).  The
 //            tokens whose destinations meet a token's source bytes form one
 //            contiguous index range (tokens are stored in output order), found
 //            once by binary search; a token is ready when those are done.
-//            k_round runs level-synchronous rounds (the dependency levels of
-//            the paper's wavefront decoder) with plain cached accesses, the
-//            kernel boundary being the only synchronisation.  The last round
+//            k_round0 (a workgroup per block, fills gathered in an LDS tile of
+//            the block's chunks that receive match bytes) and k_round run
+//            level-synchronous rounds (the dependency levels of the paper's
+//            wavefront decoder) with plain cached accesses, the kernel
+//            boundary being the only synchronisation.  The last round
 //            marks its leftovers in a bitmap, which k_pcount / k_pscatter
 //            compact into an ascending list; k_tail then finishes that deep
 //            remainder in one persistent launch, waves taking 64-token chunks
