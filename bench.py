@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, each scaled by the
 # same counter on a plain 256 MiB device copy in the same run).  They hold only
 # for the kernel source they were taken on (first 16 hex digits of its SHA-256).
-TRAFFIC_SOURCE = "183dbdfe36d7fb76"
+TRAFFIC_SOURCE = "77721789c617d885"
 TRAFFIC_MB = {  # read + write, MB per launch
     "k_ans": 138.6 + 234.6,
     "k_parse": 242.5 + 324.3,

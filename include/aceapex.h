@@ -241,7 +241,7 @@ int aceapex_closure_blocks(aceapex_decoder* dec, uint32_t n, const uint64_t* h_o
                            uint32_t threads);
 
 /* A reusable range-decode plan with capacity limits (blocks and matches of
- * one call's closure, at most 32768 blocks and 2^24 matches); its workspace
+ * one call's closure, at most 131072 blocks and 2^26 matches); its workspace
  * size depends only on the limits. */
 typedef struct aceapex_range_plan aceapex_range_plan;
 int aceapex_range_plan_create(aceapex_decoder* dec, uint64_t max_blocks, uint64_t max_tokens,

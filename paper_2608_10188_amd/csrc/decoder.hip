@@ -87,7 +87,8 @@ struct JobDev {
   uint32_t B, mm;
 };
 
-// One block of a window.  Window order is (job, block) ascending, and the
+// One block of a window.  A window holds the blocks of its jobs job by job
+// (in the plan's window order of jobs), ascending within a job, and the
 // window's tokens are stored block after block in that order.
 struct WinBlock {
   uint64_t b;       // block index in its archive
@@ -1615,7 +1616,17 @@ static int build_tables(Plan* P, const std::vector<JobSpec>& specs) {
       P->wins.push_back(cur);
       cur = Plan::Win{P->wbl.size(), 0, 0};
     };
-    for (size_t j = 0; j < specs.size(); ++j) {
+    // jobs enter the windows densest first (matches per block): a window runs
+    // as long as its deepest dependency chain, and match-dense archives carry
+    // the deep chains, so they share windows instead of lengthening every one
+    std::vector<size_t> order(specs.size());
+    for (size_t j = 0; j < order.size(); ++j) order[j] = j;
+    auto density = [&](size_t j) {
+      const aceapex_decoder* d = specs[j].dec;
+      return d->info.n_blocks ? double(d->mpre[d->info.n_blocks]) / double(d->info.n_blocks) : 0.0;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return density(x) > density(y); });
+    for (const size_t j : order) {
       const aceapex_decoder* d = specs[j].dec;
       const uint64_t nb = specs[j].blocks.empty() ? d->info.n_blocks : specs[j].blocks.size();
       for (uint64_t i = 0; i < nb; ++i) {

@@ -30,8 +30,11 @@ struct JobSpec {
   std::vector<uint64_t> blocks;
 };
 
-constexpr uint32_t kWindowBlocks = 32768;
-constexpr uint64_t kWindowTokens = uint64_t(1) << 24;
+// Window limits: a window's workspace is about 130 KiB per block plus 45 B per
+// token (about 18 GiB at these limits, sized to the blocks a plan actually
+// holds), so a batch of many archives runs in few windows.
+constexpr uint32_t kWindowBlocks = 131072;
+constexpr uint64_t kWindowTokens = uint64_t(1) << 26;
 
 int plan_create(const std::vector<JobSpec>& jobs, Plan** out);
 // Rebuild an existing plan for new jobs, reusing its device tables (grown
