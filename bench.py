@@ -319,6 +319,8 @@ def run_batch(args, log):
         batched_ms = time_it(lambda: [cb.decode(work=cw) for cb, cw in class_plans], args.steps, args.warmup)
     else:
         batch.set_option(ax.OPT_GRAPH, 1)
+        if args.bulk_rounds:
+            batch.set_option(ax.OPT_BULK_ROUNDS, args.bulk_rounds)
         batched_ms = time_it(lambda: batch.decode(work=work), args.steps, args.warmup)
     err, _ = batch.status()
 
@@ -335,7 +337,7 @@ def run_batch(args, log):
         "warmup": args.warmup, "ms_per_step": round(batched_ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"batch of {count} archives", "n_bytes": total, "archive_bytes": comp,
-                   "autotuned": bool(args.autotune)},
+                   "autotuned": bool(args.autotune), "bulk_rounds": None if args.autotune else (args.bulk_rounds or 4)},
         "plain_loop_gbs": round(total / (loop_ms / 1e3) / 1e9, 3), "plain_loop_ms": round(loop_ms, 3),
         "speedup_vs_plain_loop": round(loop_ms / batched_ms, 3), "status": [err, err2],
         "autotune": tuned or None,
