@@ -235,7 +235,8 @@ int aceapex_decoder_build_index(aceapex_decoder* dec, uint8_t* d_full, void* d_w
  * holding any byte the ranges need (their own bytes and, transitively, the
  * bytes their matches copy).  blocks may be NULL to only count; *n_tokens
  * (nullable) receives their match count.  Needs the token index.  Closures
- * run on `threads` host threads (0 = all). */
+ * run on at most `threads` host threads (0 = up to 16), one per 8 ranges at
+ * most (at most 64). */
 int aceapex_closure_blocks(aceapex_decoder* dec, uint32_t n, const uint64_t* h_offs, const uint64_t* h_lens,
                            uint64_t* h_blocks, uint64_t cap, uint64_t* n_blocks, uint64_t* n_tokens,
                            uint32_t threads);

@@ -127,7 +127,11 @@ int union_closure(const aceapex_decoder* d, uint32_t n, const uint64_t* offs, co
   for (uint32_t i = 0; i < n; ++i)
     if (offs[i] > N || lens[i] > N - offs[i]) return ax::fail(AX_E_RANGE, "range outside the archive");
   if (d->idx_dstlen.size() != d->info.n_matches) return ax::fail(AX_E_ARG, "token index not built");
-  const uint32_t T = std::max(1u, std::min(threads ? threads : std::thread::hardware_concurrency(), n ? n : 1));
+  // a thread per 8 ranges at most, 16 at most by default: a closure takes
+  // microseconds, starting a thread tens of them, and the process may see
+  // more cores than its share
+  const uint32_t T = std::max(1u, std::min({threads ? threads : std::min(16u, std::thread::hardware_concurrency()),
+                                            (n + 7) / 8, 64u}));
   std::vector<std::vector<uint64_t>> part(T);
   std::atomic<uint32_t> next{0};
   auto worker = [&](uint32_t w) {

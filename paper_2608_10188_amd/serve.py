@@ -14,6 +14,7 @@ so concurrent batches never write the same bytes.  Latency is arrival to
 completion, read from HIP events on the device timeline.
 """
 import collections
+import gc
 import time
 
 import numpy as np
@@ -50,10 +51,21 @@ class Server:
         of lens[i] bytes).  Returns a dict with per-request latency (ns,
         device timeline), host-observed latency (ns) and batch statistics.
         max_batch=1 with slots=1 serves one request at a time, in order."""
+        max_batch = max_batch or self.max_batch
+        # the collector would stop the loop for tens of milliseconds now and
+        # then (every batch allocates events and lists): off while serving
+        gc_was_on = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(arrivals_ns, offs, lens, outs, realtime, max_batch, slots)
+        finally:
+            if gc_was_on:
+                gc.enable()
+
+    def _run(self, arrivals_ns, offs, lens, outs, realtime, max_batch, slots):
         import torch
 
         n = len(offs)
-        max_batch = max_batch or self.max_batch
         arrivals = np.asarray(arrivals_ns, dtype=np.int64)
         free = collections.deque(range(min(len(self.slots), slots or len(self.slots))))
         inflight = {}
