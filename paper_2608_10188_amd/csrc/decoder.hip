@@ -291,22 +291,26 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
   uint32_t wa = fetch(lane), w1 = fetch(64 + lane), w2 = fetch(128 + lane);
   uint32_t ptr = 0;
   const uint32_t steps = (n + K - 1) / K;
-  // steps with all 64 lanes decoding: no per-lane bounds, the store address
-  // a wave-uniform base plus the lane
-  const uint32_t full = K == 64 ? n / 64 : 0;
+  // steps with all K lanes decoding: no per-lane bounds, the store address
+  // a wave-uniform base plus the lane.  Every lane runs the step (the word
+  // permute reads all 64 lanes' window); lanes >= K are left out of the
+  // ballot and the store
+  const uint32_t full = n / K;
+  const uint64_t kmask = K == 64 ? ~0ull : ((1ull << K) - 1ull);
+  const bool decoding = lane < K;
   AX_GLOBAL uint8_t* ob = out;
-  for (uint32_t t = 0; t < full; ++t, ob += 64) {
+  for (uint32_t t = 0; t < full; ++t, ob += K) {
     const uint32_t slot = x & (ax::kProbScale - 1);
     const uint32_t s = symtab[slot];
     const uint32_t fc = fctab[s];
     const uint32_t xn = (fc & 0xFFFFu) * (x >> ax::kProbBits) + slot - (fc >> 16);
-    const uint64_t m = __builtin_amdgcn_ballot_w64(xn < ax::kRansLow);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(xn < ax::kRansLow) & kmask;
     const uint32_t q = ptr - base + lanes_below(m);  // < 128; the permute takes the lane mod 64
     const uint32_t va = __builtin_amdgcn_ds_bpermute(int(q << 2), int(wa));
     const uint32_t vb = __builtin_amdgcn_ds_bpermute(int(q << 2), int(w1));
     const uint32_t w = q < 64 ? va : vb;
     x = xn < ax::kRansLow ? ((xn << 16) | w) : xn;
-    ob[lane] = uint8_t(s);
+    if (decoding) ob[lane] = uint8_t(s);
     ptr += __popcll(m);
     if (ptr - base >= 64) {
       base += 64;
@@ -315,7 +319,7 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
       w2 = fetch(base + 128 + lane);
     }
   }
-  uint32_t i = full * 64 + lane;
+  uint32_t i = full * K + lane;
   for (uint32_t t = full; t < steps; ++t, i += K) {
     const bool act = lane < K && i < n;
     const uint32_t slot = x & (ax::kProbScale - 1);
