@@ -58,6 +58,22 @@ def test_config1_shape(kind):
     check(f"config1-{kind}", x, arc)
 
 
+@pytest.mark.parametrize("kind", ["dna", "text"])
+def test_full_size_workloads(kind):
+    """The benchmark's workloads at full size (253,952,000 B DNA seed 2 and
+    209,715,200 B text seed 3) in the launch configuration it times (default
+    options), every byte against the oracle's decode, in both copy modes.
+    The archive comes from the library's host encoder (the oracle encoder
+    would take minutes at this size); the oracle's decode of it must equal
+    the input first, so the archive is an input pinned by the oracle."""
+    if kind == "dna":
+        x = synth.dna(15500 * B, 2)
+    else:
+        x = synth.text(209715200, 3)
+    arc = ax.encode(x, threads=16)
+    check(f"full-{kind}", x, arc)
+
+
 def test_no_rep_encoding():
     x = synth.dna(2 << 20, 7)
     arc, st = oracle.encode(x, no_rep=1)
