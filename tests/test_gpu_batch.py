@@ -80,3 +80,40 @@ def test_batch_with_empty_and_tiny_archives():
     assert err == 0
     for x, g in zip(xs, got):
         assert np.array_equal(g, x)
+
+
+def test_full_size_batch_sampled():
+    """The benchmark's batch at full size (4096 archives, 64 KiB-64 MiB,
+    60 % DNA / 40 % text, plan seed 4, archive i seeded 1000 + i), one plan
+    as timed: every archive against the XXH3 of its input, 64 archives drawn
+    at random byte by byte against the oracle's decode.  Archives come from
+    the library's host encoder; each sampled one is pinned by the oracle's
+    decode equalling its input."""
+    import concurrent.futures as cf
+
+    xxhash = pytest.importorskip("xxhash")
+    sizes, kinds = synth.batch_plan(4096, 4)
+
+    def make(i):
+        x = synth.dna(int(sizes[i]), 1000 + i) if kinds[i] == 0 else synth.text(int(sizes[i]), 1000 + i)
+        return ax.encode(x, threads=1), xxhash.xxh3_64_intdigest(x.tobytes()), x.size
+
+    with cf.ThreadPoolExecutor(max_workers=16) as pool:
+        made = list(pool.map(make, range(4096)))
+    decs, outs = [], []
+    for arc, _, n in made:
+        decs.append(ax.Decoder(arc, torch.from_numpy(arc).cuda()))
+        outs.append(torch.full((max(16, n),), 0xCC, dtype=torch.uint8, device="cuda"))
+    bt = ax.Batch(decs, outs)
+    _say("batch4096 full size")
+    bt.decode()
+    err, bad = bt.status()
+    assert err == 0, f"device status {err} at block {bad}"
+    sample = set(np.random.default_rng(4).choice(4096, 64, replace=False).tolist())
+    for i, ((arc, h, n), o) in enumerate(zip(made, outs)):
+        got = o[:n].cpu().numpy()
+        assert xxhash.xxh3_64_intdigest(got.tobytes()) == h, f"archive {i}"
+        if i in sample:
+            ref = oracle.decode(arc)
+            assert xxhash.xxh3_64_intdigest(ref.tobytes()) == h, f"archive {i}: oracle"
+            assert np.array_equal(got, ref), f"archive {i}"
