@@ -387,7 +387,7 @@ def run_batch(args, log):
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batch":
         run_batch(args, log)

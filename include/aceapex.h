@@ -41,7 +41,7 @@ enum {
   AX_OK = 0,
   AX_E_ARG = -1,         /* bad argument (null pointer, size too small, ...) */
   AX_E_CORRUPT = -2,     /* the archive violates the format */
-  AX_E_UNSUPPORTED = -3, /* valid but outside what this build decodes */
+  AX_E_UNSUPPORTED = -3, /* valid but outside what this library decodes */
   AX_E_CAPACITY = -4,    /* caller buffer or workspace too small */
   AX_E_HIP = -5,         /* a HIP runtime call failed */
   AX_E_RANGE = -6,       /* byte range outside the archive */

@@ -109,15 +109,15 @@ def splitmix64(state, count):
     return [_load().axs_splitmix64(ctypes.byref(st)) for _ in range(count)]
 
 
-# Workloads: (generator, n_bytes, seed)
-CONFIGS = {
-    1: ("dna", 4 * 1024 * 1024, 1),
-    2: ("dna", 15500 * 16384, 2),
-    3: ("text", 209715200, 3),
+# Named workloads: (generator, n_bytes, seed)
+WORKLOADS = {
+    "dna4": ("dna", 4 * 1024 * 1024, 1),
+    "dna254": ("dna", 15500 * 16384, 2),
+    "text200": ("text", 209715200, 3),
 }
 
 
-def config_input(k, n=None):
-    kind, size, seed = CONFIGS[k]
+def workload_input(name, n=None):
+    kind, size, seed = WORKLOADS[name]
     size = size if n is None else n
     return dna(size, seed) if kind == "dna" else text(size, seed)
