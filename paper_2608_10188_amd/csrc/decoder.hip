@@ -636,16 +636,18 @@ __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
     const uint32_t n_tokc = uint32_t(ctot >> 48);
     // length and offset values of this chunk
     uint64_t* lv64 = sh.offval;  // reuse: lengths first, then offsets
-    if (!(len_lds ? leb_values<kLenBpt>(static_cast<const uint8_t*>(sh.lenb), n_len, &lenc, n_esc, lv64, sh)
-                  : leb_values<kLenBpt>(leng, n_len, &lenc, n_esc, lv64, sh))) {
-      failed = true;
-      break;
+    if (n_esc) {  // most chunks hold no escaped length (n_esc is the same for the whole block)
+      if (!(len_lds ? leb_values<kLenBpt>(static_cast<const uint8_t*>(sh.lenb), n_len, &lenc, n_esc, lv64, sh)
+                    : leb_values<kLenBpt>(leng, n_len, &lenc, n_esc, lv64, sh))) {
+        failed = true;
+        break;
+      }
+      if (t < n_esc) {
+        const uint64_t e = lv64[t];
+        sh.lenval[t] = e > B ? 0xFFFFFFFFu : uint32_t(e);
+      }
+      __syncthreads();
     }
-    if (t < n_esc) {
-      const uint64_t e = lv64[t];
-      sh.lenval[t] = e > B ? 0xFFFFFFFFu : uint32_t(e);
-    }
-    __syncthreads();
     if (!(off_lds ? leb_values<kOffBpt>(static_cast<const uint8_t*>(sh.offb), n_off, &offc, n_k1, sh.offval, sh)
                   : leb_values<kOffBpt>(offg, n_off, &offc, n_k1, sh.offval, sh))) {
       failed = true;
