@@ -35,12 +35,12 @@ HBM_PEAK_GBS = 8000.0
 # two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, each scaled by the
 # same counter on a plain 256 MiB device copy in the same run).  They hold only
 # for the kernel source they were taken on (first 16 hex digits of its SHA-256).
-TRAFFIC_SOURCE = "e58fcf86e7537a70"
+TRAFFIC_SOURCE = "57837e9509947b0c"
 TRAFFIC_MB = {  # read + write, MB per launch
     "k_ans": 138.6 + 234.6,
     "k_parse": 242.5 + 324.3,
     # k_clear2, k_round0, k_long, k_round x 3, k_pcount, k_pscatter, k_tail
-    "copy": (0.0 + 0.4) + (304.2 + 125.1) + (0.1 + 0.1) + 3 * (115.2 + 16.0) + (0.4 + 0.0) + (0.4 + 0.2) + (22.6 + 19.9),
+    "copy": (0.0 + 0.4) + (304.3 + 125.1) + (0.1 + 0.1) + 3 * (115.2 + 16.0) + (0.4 + 0.0) + (0.4 + 0.2) + (22.5 + 19.9),
 }
 
 WORKLOADS = {
