@@ -69,7 +69,7 @@ def lib():
                                         ctypes.c_uint32, u8p, u32p, ctypes.c_uint32, u8p, u32p]
         L.axo_block_parse.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, P(Cmd), ctypes.c_uint64, u64p]
         L.axo_depths.argtypes = [u8p, ctypes.c_uint64, u32p, ctypes.c_uint64, u32p]
-        L.axo_block_levels.argtypes = [u8p, ctypes.c_uint64, u32p, u32p]
+        L.axo_block_levels.argtypes = [u8p, ctypes.c_uint64, u32p, u32p, u32p, u32p]
         L.axo_closure.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, u8p, u64p]
         L.axo_stream_encode.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
                                         P(u8p), u32p]
@@ -217,12 +217,21 @@ def depths(arc):
     return d[:m], mx.value
 
 
-def block_levels(arc):
+def block_levels(arc, per_block=False):
+    """Maxima of the raw and match-sourced block levels; with per_block=True
+    also the level of every block: (raw_max, msrc_max, raw[], msrc[])."""
     a = _arr(arc)
     r, m = ctypes.c_uint32(), ctypes.c_uint32()
-    rc = lib().axo_block_levels(_u8(a), a.size, ctypes.byref(r), ctypes.byref(m))
+    nb = info(a).n_blocks
+    raw = np.zeros(max(1, nb), np.uint32)
+    msrc = np.zeros(max(1, nb), np.uint32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    rc = lib().axo_block_levels(_u8(a), a.size, ctypes.byref(r), ctypes.byref(m), raw.ctypes.data_as(u32p),
+                                msrc.ctypes.data_as(u32p))
     if rc:
         raise OracleError(rc, "block_levels")
+    if per_block:
+        return r.value, m.value, raw[:nb], msrc[:nb]
     return r.value, m.value
 
 

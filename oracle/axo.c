@@ -334,10 +334,13 @@ int axo_stream_decode(const uint8_t* rec, uint32_t len, uint8_t* out, uint32_t c
 
 typedef struct {
   buf_t lit, len, off, cmd;
-  uint64_t n_matches;
+  uint64_t n_matches, n_lit_cmds, n_escapes;
 } blockstreams_t;
 
-static void bs_reset(blockstreams_t* s) { s->lit.n = s->len.n = s->off.n = s->cmd.n = 0; s->n_matches = 0; }
+static void bs_reset(blockstreams_t* s) {
+  s->lit.n = s->len.n = s->off.n = s->cmd.n = 0;
+  s->n_matches = s->n_lit_cmds = s->n_escapes = 0;
+}
 static void bs_free(blockstreams_t* s) { free(s->lit.p); free(s->len.p); free(s->off.p); free(s->cmd.p); }
 static int bs_oom(const blockstreams_t* s) { return s->lit.oom || s->len.oom || s->off.oom || s->cmd.oom; }
 
@@ -345,17 +348,18 @@ static int bs_oom(const blockstreams_t* s) { return s->lit.oom || s->len.oom || 
 static void emit_lit(blockstreams_t* s, const uint8_t* lits, uint64_t len) {
   buf_put(&s->lit, lits, len);
   if (len - 1 < 63) buf_u8(&s->cmd, (uint8_t)((len - 1) << 2));
-  else { buf_u8(&s->cmd, (uint8_t)(63 << 2)); buf_leb(&s->len, len - 64); }
+  else { buf_u8(&s->cmd, (uint8_t)(63 << 2)); buf_leb(&s->len, len - 64); s->n_escapes++; }
+  s->n_lit_cmds++;
 }
 static void emit_match(blockstreams_t* s, uint64_t src, uint64_t len, uint32_t mm) {
   if (len - mm < 63) buf_u8(&s->cmd, (uint8_t)(1 | ((len - mm) << 2)));
-  else { buf_u8(&s->cmd, (uint8_t)(1 | (63 << 2))); buf_leb(&s->len, len - 63 - mm); }
+  else { buf_u8(&s->cmd, (uint8_t)(1 | (63 << 2))); buf_leb(&s->len, len - 63 - mm); s->n_escapes++; }
   buf_leb(&s->off, src);
   s->n_matches++;
 }
 static void emit_rep(blockstreams_t* s, uint32_t r, uint64_t len, uint32_t mm) {
   if (len - mm < 15) buf_u8(&s->cmd, (uint8_t)(2 | (r << 2) | ((len - mm) << 4)));
-  else { buf_u8(&s->cmd, (uint8_t)(2 | (r << 2) | (15 << 4))); buf_leb(&s->len, len - 15 - mm); }
+  else { buf_u8(&s->cmd, (uint8_t)(2 | (r << 2) | (15 << 4))); buf_leb(&s->len, len - 15 - mm); s->n_escapes++; }
   s->n_matches++;
 }
 
@@ -500,6 +504,8 @@ static int encode_pass(const uint8_t* in, uint64_t n, const axo_params* p, const
     if (bs_oom(&s)) { rc = AXO_E_NOMEM; goto out; }
     if (st) {
       st->n_commands += s.cmd.n;
+      st->n_lit_cmds += s.n_lit_cmds;
+      st->n_escapes += s.n_escapes;
       st->n_matches += s.n_matches;
       st->n_lit_bytes += s.lit.n;
     }
@@ -914,7 +920,8 @@ int axo_depths(const uint8_t* arc, uint64_t len, uint32_t* depth, uint64_t cap, 
   return rc;
 }
 
-int axo_block_levels(const uint8_t* arc, uint64_t len, uint32_t* raw_max, uint32_t* msrc_max) {
+int axo_block_levels(const uint8_t* arc, uint64_t len, uint32_t* raw_max, uint32_t* msrc_max, uint32_t* raw_lvl,
+                     uint32_t* msrc_lvl) {
   axo_info in;
   int rc = axo_read_info(arc, len, &in);
   if (rc) return rc;
@@ -945,6 +952,10 @@ int axo_block_levels(const uint8_t* arc, uint64_t len, uint32_t* raw_max, uint32
   }
   *raw_max = mr;
   *msrc_max = mmx;
+  for (uint64_t b = 0; b < in.n_blocks; b++) {
+    if (raw_lvl) raw_lvl[b] = lr[b];
+    if (msrc_lvl) msrc_lvl[b] = lm[b];
+  }
   free(cmds); free(bym); free(lr); free(lm);
   return AXO_OK;
 }

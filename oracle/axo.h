@@ -21,9 +21,12 @@
  * Byte layout, entropy-coder constants and greedy tie-breaks are readings of
  * the paper where it is silent; they are listed with the format below.
  *
- * Parity status: every function here is pinned by the CPU tests (round
- * trips, closed forms, brute force, hand-derived golden fixtures, the paper's
- * invariants).  No function is "parity unpinned".
+ * Parity status: every function here is pinned by the CPU tests against
+ * something other than itself: round trips, closed forms, brute force over
+ * the recursive definitions (depth, block levels, closure), hand-derived
+ * golden fixtures (history walk, periodic fill, depth chain, block levels)
+ * and the paper's invariants.  The encoder statistics n_lit_cmds and
+ * n_escapes are pinned by recounting the decoded command streams.
  */
 #ifndef AXO_H
 #define AXO_H
@@ -51,6 +54,8 @@ typedef struct {
 
 void axo_params_default(axo_params* p);
 
+/* Encoder statistics.  n_lit_cmds: literal-run commands; n_escapes:
+ * commands whose length continues in the length stream. */
 typedef struct {
   uint64_t n_bytes, n_blocks, comp_bytes;
   uint64_t n_commands, n_lit_cmds, n_matches, n_rep, n_escapes, n_match_bytes, n_lit_bytes;
@@ -123,8 +128,10 @@ int axo_depths(const uint8_t* arc, uint64_t len, uint32_t* depth, uint64_t cap,
  *                of the other blocks its sources touch;
  *  match-sourced: the same, counting only bytes of other blocks that were
  *                written by matches.
- * Returns the maxima. */
-int axo_block_levels(const uint8_t* arc, uint64_t len, uint32_t* raw_max, uint32_t* msrc_max);
+ * Returns the maxima, and when raw_lvl / msrc_lvl are not NULL the level of
+ * every block (n_blocks entries each). */
+int axo_block_levels(const uint8_t* arc, uint64_t len, uint32_t* raw_max, uint32_t* msrc_max, uint32_t* raw_lvl,
+                     uint32_t* msrc_lvl);
 
 /* Byte-precise source closure of the output range [off, off+n): marks in
  * block_mask[] (one byte per block) every block whose bytes are needed to

@@ -399,12 +399,91 @@ def test_closure_matches_bruteforce():
         assert np.array_equal(got, want) and k == int(want.sum())
 
 
-def test_block_levels_bounds():
-    x = synth.dna(200000, 24)
-    arc, _ = oracle.encode(x, block_size=4096)
-    raw, msrc = oracle.block_levels(arc)
-    nb = oracle.info(arc).n_blocks
-    assert 0 <= msrc <= raw <= nb - 1
+def _levels_by_recursion(arc):
+    """Block levels evaluated from their recursive definitions over the
+    writer map (block by block, memoised), not by the oracle's forward pass:
+    raw(b) = 0 if every source byte of b's matches lies in b, else 1 + the
+    largest raw level of the other blocks those bytes lie in; msrc(b) the
+    same over source bytes of other blocks that a match wrote."""
+    c, w = _writer_map(arc)
+    inf = oracle.info(arc)
+    B, nb = inf.block_size, inf.n_blocks
+    touched = [set() for _ in range(nb)]    # other blocks read by block b
+    touched_m = [set() for _ in range(nb)]  # the same, match-written bytes only
+    for cmd in c:
+        if cmd["kind"] == 0:
+            continue
+        b = int(cmd["dst"]) // B
+        dist = int(cmd["dst"] - cmd["src"])
+        for q in range(int(cmd["src"]), int(cmd["src"]) + min(int(cmd["len"]), dist)):
+            if q // B != b:
+                touched[b].add(q // B)
+                if c[int(w[q])]["kind"] != 0:
+                    touched_m[b].add(q // B)
+    memo = {}
+
+    def level(b, sets):
+        key = (b, id(sets))
+        if key not in memo:
+            memo[key] = 0 if not sets[b] else 1 + max(level(o, sets) for o in sets[b])
+        return memo[key]
+
+    import sys
+    sys.setrecursionlimit(100000)
+    return [level(b, touched) for b in range(nb)], [level(b, touched_m) for b in range(nb)]
+
+
+def test_golden_block_levels():
+    ex = {}
+    cmds = []
+    with open(os.path.join(GOLDEN, "block_levels.txt")) as f:
+        for line in f:
+            line = line.rstrip("\n")
+            if not line or line.startswith("#"):
+                continue
+            key, _, val = line.partition(":")
+            if key == "cmd":
+                cmds.append(tuple(map(int, val.split())))
+            else:
+                ex[key] = val.strip()
+    n, pat = int(ex["n"]), ex["literal_pattern"].encode()
+    data = bytearray(n)
+    for kind, dst, ln, src, _ in cmds:  # literals from the pattern, matches copied byte by byte
+        for k in range(ln):
+            data[dst + k] = pat[(dst + k) % len(pat)] if kind == 0 else data[src + k]
+    assert sum(c[2] for c in cmds) == n
+    arc = oracle.assemble(bytes(data), cmds, block_size=int(ex["block_size"]))
+    assert oracle.decode(arc).tobytes() == bytes(data)
+    raw_max, msrc_max, raw, msrc = oracle.block_levels(arc, per_block=True)
+    assert list(raw) == [int(v) for v in ex["raw_levels"].split()]
+    assert list(msrc) == [int(v) for v in ex["msrc_levels"].split()]
+    assert (raw_max, msrc_max) == (3, 2)
+
+
+def test_block_levels_match_recursive_definition():
+    for x in (synth.dna(120000, 24), synth.text(120000, 26)):
+        arc, _ = oracle.encode(x, block_size=4096)
+        raw_max, msrc_max, raw, msrc = oracle.block_levels(arc, per_block=True)
+        want_raw, want_msrc = _levels_by_recursion(arc)
+        assert list(raw) == want_raw and list(msrc) == want_msrc
+        assert raw_max == max(want_raw) and msrc_max == max(want_msrc)
+        assert 0 <= msrc_max <= raw_max <= oracle.info(arc).n_blocks - 1
+
+
+def test_encoder_command_counters_match_the_streams():
+    """n_lit_cmds and n_escapes recounted from every block's decoded command
+    stream (a literal run escapes at length field 63; a match at 63; a
+    repeat at 15)."""
+    for x in (synth.dna(200000, 27), synth.text(200000, 28)):
+        arc, st = oracle.encode(x, block_size=4096)
+        lit = esc = 0
+        for b in range(oracle.info(arc).n_blocks):
+            for c in oracle.block_streams(arc, b)["cmd"].tolist():
+                kind = c & 3
+                lit += kind == 0
+                esc += (c >> 2) == 63 if kind in (0, 1) else (c >> 4) == 15
+        assert (st.n_lit_cmds, st.n_escapes) == (lit, esc)
+        assert st.n_escapes > 0 and st.n_lit_cmds > 0
 
 
 # -------------------------------------------------------------- corruption --
