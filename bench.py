@@ -31,17 +31,13 @@ sys.path.insert(0, ROOT)
 METRIC = "decoded GB/s device-resident (254 MB DNA) vs HBM peak; p50/p99 us per 16 KB read"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of each decode kernel on the 254 MB DNA workload, from
-# two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, each scaled by the
-# same counter on a plain 256 MiB device copy in the same run).  They hold only
-# for the kernel source they were taken on (first 16 hex digits of its SHA-256).
-TRAFFIC_SOURCE = "57837e9509947b0c"
-TRAFFIC_MB = {  # read + write, MB per launch
-    "k_ans": 138.6 + 234.6,
-    "k_parse": 242.5 + 324.3,
-    # k_clear2, k_round0, k_long, k_round x 3, k_pcount, k_pscatter, k_tail
-    "copy": (0.0 + 0.4) + (304.3 + 125.1) + (0.1 + 0.1) + 3 * (115.2 + 16.0) + (0.4 + 0.0) + (0.4 + 0.2) + (22.5 + 19.9),
-}
+# HBM bytes moved by one whole decode of the 254 MB DNA workload (all its
+# kernels), from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE,
+# each scaled by the same counter on a plain 256 MiB device copy in the same
+# run).  They hold only for the decoder source they were taken on (first 16
+# hex digits of its SHA-256); otherwise the line reports traffic null.
+TRAFFIC_SOURCE = ""
+TRAFFIC_MB = None  # read + write MB per decode
 
 WORKLOADS = {
     # name: (generator, bytes, seed, description)
@@ -82,6 +78,8 @@ def parse_args():
     ap.add_argument("--tail-chunks", type=int, default=0, help="chunks per persistent-launch ticket (0 = default)")
     ap.add_argument("--fill", default="", help="fill modes 'R,T' for rounds and tail (0 lane/wave, 1 segmented)")
     ap.add_argument("--graph", type=int, default=0, help="1: each decode replays the plan captured as one hipGraph")
+    ap.add_argument("--tail-mode", type=int, default=0, help="deep remainder: 0 pointer jumping, 1 persistent chase")
+    ap.add_argument("--jump-passes", type=int, default=0, help="at most this many jump passes (0 = automatic)")
     return ap.parse_args()
 
 
@@ -89,19 +87,66 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(arc, n_bytes):
-    """The oracle's sequential decode on one host core, over the whole archive
-    (a bounded ~3-10 s of CPU work at this size)."""
+def host_cpu():
+    """Host CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(arc, n_bytes, x):
+    """The oracle's sequential decode on one host core over the whole archive
+    (median of 5, about 3 s of CPU work at this size), and its encoder on a
+    bounded 32 MiB prefix of the input (about 10 s)."""
     import oracle
 
     times = []
-    for _ in range(3):
+    for _ in range(5):
         t = time.perf_counter()
         oracle.decode(arc, verify=False)
         times.append(time.perf_counter() - t)
     t = float(np.median(times))
+    prefix = x[: 32 << 20]
+    t0 = time.perf_counter()
+    oracle.encode(prefix)
+    enc_s = time.perf_counter() - t0
     return {"value": n_bytes / t / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"whole archive ({n_bytes} B), median of 3 single-threaded oracle decodes, {t:.2f} s each"}
+            "sample": f"whole archive ({n_bytes} B), median of 5 single-threaded oracle decodes "
+                      f"(min {min(times):.3f} s, max {max(times):.3f} s)",
+            "encode_gbs": round(prefix.size / enc_s / 1e9, 5),
+            "encode_sample": f"oracle encoder on the first {prefix.size} B of the input, {enc_s:.2f} s",
+            "host": host_cpu()}
+
+
+def store_probe(torch, dev, n_bytes, reps=20):
+    """Coalesced-write ceiling on this GPU: torch's fill of an n-byte buffer
+    (a plain store kernel, 16-byte vector stores) and a device copy of the
+    same size, timed with events; GB/s of bytes written."""
+    a = torch.empty(n_bytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    out = {}
+    for name, fn in (("fill", lambda: a.fill_(7)), ("copy", lambda: b.copy_(a))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "written_gbs": round(n_bytes / ms / 1e6, 1)}
+    out["copy"]["moved_gbs"] = round(2 * n_bytes / out["copy"]["ms"] / 1e6, 1)
+    del a, b
+    return out
 
 
 def _pcts(ns):
@@ -430,6 +475,10 @@ def main():
         dec.set_option(ax.OPT_FILL_TAIL, ft)
     if args.graph:
         dec.set_option(ax.OPT_GRAPH, 1)
+    if args.tail_mode:
+        dec.set_option(ax.OPT_TAIL_MODE, args.tail_mode)
+    if args.jump_passes:
+        dec.set_option(ax.OPT_JUMP_PASSES, args.jump_passes)
     stream = torch.cuda.current_stream()
     if args.calib_copy_mib:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE under a
@@ -456,23 +505,25 @@ def main():
         dec.decode_all(out=out, copy_mode=mode)
     torch.cuda.synchronize()
     # throughput: K back-to-back decodes on the stream, bracketed by events
+    # (one event before each step as well, for the per-step spread)
     t_start = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for k in range(args.steps):
         dec.decode_all(out=out, copy_mode=mode)
-    ev1.record(stream)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms = evs[0].elapsed_time(evs[-1])
+    step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
     # stage split: K more decodes with the library's stage events (HIP events
-    # recorded on the decode stream between the rANS, parse and copy kernels)
+    # recorded on the decode stream around the rANS, parse, bulk-round and
+    # remainder kernels of every window)
     dec.set_timing(True)
-    stage = np.zeros(3)
+    stage = np.zeros(4)
     for _ in range(args.steps):
         dec.decode_all(out=out, copy_mode=mode)
-        stage += np.array(dec.stage_ms())  # waits for this decode's last event
+        stage += np.array(dec.stage_ms(remainder=True))  # waits for this decode's last event
     dec.set_timing(False)
     err, bad = dec.status()
     if err:
@@ -480,10 +531,11 @@ def main():
         sys.exit(1)
     ms_per_step = gpu_ms / args.steps
     value = n / (ms_per_step / 1e3) / 1e9
-    ans_ms, parse_ms, copy_ms = (stage / args.steps).tolist()
+    ans_ms, parse_ms, copy_ms, rem_ms = (stage / args.steps).tolist()
 
-    # algorithmic bytes per decode: output N, compressed archive C, match
-    # source bytes S = sum over matches of min(len, dist)
+    # algorithmic bytes per decode (the HBM floor of the whole path): output
+    # N written, compressed archive C read, match sources S = sum over matches
+    # of min(len, dist) read
     s_bytes = int(st.n_src_bytes)
     match_bytes = int(st.n_match_bytes)
     c_bytes = int(arc.size)
@@ -491,27 +543,30 @@ def main():
     d_bytes = int(st.n_lit_bytes + st.n_commands + st.n_off_bytes + st.n_len_bytes)  # decoded stream symbols
 
     stages = {"ans": ans_ms, "parse": parse_ms, "copy": copy_ms}
-    dom = max(stages, key=stages.get)
-    # per-kernel algorithmic bytes (stated in the design notes):
+    # per-stage algorithmic bytes (extras; byte definitions in the design notes):
     #   ans:   read compressed payload C, write decoded stream symbols D
-    #   parse: read decoded symbols D, write the output N (tile) and tokens
+    #   parse: read decoded symbols D, write the output N (tile) and tokens (16 B per match)
     #   copy:  read match sources S, write match bytes M
     alg = {"ans": c_bytes + d_bytes, "parse": d_bytes + n + 16 * st.n_matches, "copy": s_bytes + match_bytes}
-    achieved = alg[dom] / (stages[dom] / 1e3) / 1e9
-    kernels = {"ans": "k_ans", "parse": "k_parse",
-               "copy": "match layer (k_clear2, k_round0, k_long, k_round x rounds, k_pcount, k_pscatter, k_tail)"}
     import hashlib
 
     src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_2608_10188_amd", "csrc", "decoder.hip"), "rb").read())
     traffic = None
     defaults = not (args.no_rep or args.syms_per_lane or args.depth_cap or args.bulk_rounds or args.fill
-                    or args.tail_chunks or args.copy != "periodic")
-    if args.workload == "dna254" and defaults and src_hash.hexdigest()[:16] == TRAFFIC_SOURCE:
-        traffic = int(TRAFFIC_MB["copy" if dom == "copy" else kernels[dom]] * 1e6)
+                    or args.tail_chunks or args.copy != "periodic" or args.tail_mode or args.jump_passes)
+    if (args.workload == "dna254" and defaults and TRAFFIC_MB is not None
+            and src_hash.hexdigest()[:16] == TRAFFIC_SOURCE):
+        traffic = int(TRAFFIC_MB * 1e6)
+    achieved = b_alg / (ms_per_step / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": kernels[dom],
-                "pipeline_alg_bytes": b_alg,
-                "pipeline_frac": round(b_alg / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 5)}
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "kernel": "whole decode (every kernel of one aceapex_decode_all)",
+                "alg_bytes": b_alg, "alg_def": "N + C + S: output, compressed archive, match sources",
+                "stages": {k: {"alg_bytes": int(alg[k]), "ms": round(stages[k], 4),
+                               "achieved_gbs": round(alg[k] / (stages[k] / 1e3) / 1e9, 2)} for k in stages}}
+    probe = store_probe(torch, dev, n)
+    probe["decoded_frac_of_fill"] = round(value / probe["fill"]["written_gbs"], 5)
+    probe["alg_frac_of_copy"] = round(achieved / probe["copy"]["moved_gbs"], 5)
 
     res = {
         "metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -522,9 +577,14 @@ def main():
                    "commands": int(st.n_commands), "matches": int(st.n_matches), "repeats": int(st.n_rep),
                    "copy_mode": args.copy, "no_rep": bool(args.no_rep), "depth_cap": args.depth_cap,
                    "max_depth": int(st.max_depth) if args.depth_cap else None, "bulk_rounds": args.bulk_rounds or 4, "fill": args.fill or "0,0", "tail_chunks": args.tail_chunks or 1,
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "tail_mode": "chase" if args.tail_mode else "jump",
+                   "jump_passes": args.jump_passes or "auto"},
         "decoded_frac_of_hbm_peak": round(value / HBM_PEAK_GBS, 5),
+        "step_ms": {"min": round(float(step_ms.min()), 4), "median": round(float(np.median(step_ms)), 4),
+                    "max": round(float(step_ms.max()), 4)},
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+        "remainder_ms": round(rem_ms, 4),
+        "store_probe": probe,
         "stage_share": {k: round(v / max(1e-9, sum(stages.values())), 4) for k, v in stages.items()},
         "wall_s": round(wall, 3),
         "roofline": roofline,
@@ -535,7 +595,7 @@ def main():
         res["read_16k"] = read_latency(ax, dec, x, out, args.reads, 16384, 54, 32768, 1 << 23)
         log(f"16 KiB reads: {res['read_16k']} ({time.time() - t0:.1f}s)")
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(arc, n)
+        res["cpu_baseline"] = cpu_baseline(arc, n, x)
     print(json.dumps(res), flush=True)
 
 

@@ -151,12 +151,15 @@ enum { AX_COPY_PERIODIC = 0, AX_COPY_SERIAL = 1 };
 int aceapex_decode_all(aceapex_decoder* dec, uint8_t* d_out, uint64_t out_cap, void* d_work, uint64_t work_len,
                        int copy_mode, void* stream);
 
-/* Stage timing of the last decode on this handle (HIP events on `stream`),
- * in milliseconds: entropy (rANS of the four streams), parse (commands,
- * literal placement, token emission), copy (match layer). Blocks on the
+/* Stage timing of the last decode on this handle (HIP events on `stream`,
+ * recorded around the stages of every window and summed), in milliseconds:
+ * entropy (rANS of the four streams), parse (commands, literal placement,
+ * token emission), copy (the whole match layer); remainder (nullable) is the
+ * part of copy spent on the tokens the bulk rounds left.  Blocks on the
  * events. */
-int aceapex_decoder_stage_ms(aceapex_decoder* dec, float* ans_ms, float* parse_ms, float* copy_ms);
-/* 1 = record stage events on later decodes (adds three event records). */
+int aceapex_decoder_stage_ms(aceapex_decoder* dec, float* ans_ms, float* parse_ms, float* copy_ms,
+                             float* remainder_ms);
+/* 1 = record stage events on later decodes (five event records per window). */
 int aceapex_decoder_set_timing(aceapex_decoder* dec, int enable);
 
 /* Decoder options (schedule knobs; none changes a decoded byte).
@@ -184,6 +187,20 @@ enum { AX_OPT_TAIL_CHUNKS = 4, AX_OPT_GRAPH = 5 };
  *     back as 16-byte stores (default); 0 = one wave per 64 tokens writing
  *     the fills straight to global memory (fill mode AX_OPT_FILL_ROUNDS). */
 enum { AX_OPT_ROUND0_TILE = 6 };
+/*   AX_OPT_TAIL_MODE  how the tokens left after the bulk rounds (the deep
+ *     remainder) are finished: 0 = pointer jumping over their bytes — every
+ *     byte names the byte its value comes from, and each of about
+ *     log2(chain length) passes replaces that name by the one it names
+ *     (default); 1 = one persistent launch that copies each token once the
+ *     tokens writing its sources are done (one dependency hop at a time; the
+ *     serial copy mode always finishes this way). */
+enum { AX_OPT_TAIL_MODE = 7 };
+/*   AX_OPT_JUMP_PASSES  0 = automatic: the first decode runs enough passes
+ *     for any chain of the window (log2 of its token count) and later ones the
+ *     count the device reported as needed, plus one; k in [1, 32] = at most k
+ *     passes.  The final gather follows whatever entries the passes left, so
+ *     the count changes timing only, never a byte. */
+enum { AX_OPT_JUMP_PASSES = 8 };
 int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
 
 /* Read the device status word of a workspace after the work queued on
@@ -215,7 +232,7 @@ void aceapex_batch_destroy(aceapex_batch* batch);
 int aceapex_batch_workspace(const aceapex_batch* batch, uint64_t* bytes);
 int aceapex_batch_set_option(aceapex_batch* batch, int option, int64_t value);
 int aceapex_batch_set_timing(aceapex_batch* batch, int enable);
-int aceapex_batch_stage_ms(aceapex_batch* batch, float* ans_ms, float* parse_ms, float* copy_ms);
+int aceapex_batch_stage_ms(aceapex_batch* batch, float* ans_ms, float* parse_ms, float* copy_ms, float* remainder_ms);
 /* Decode every job; asynchronous on `stream`; status via
  * aceapex_workspace_status. */
 int aceapex_decode_batch(aceapex_batch* batch, void* d_work, uint64_t work_len, int copy_mode, void* stream);

@@ -29,6 +29,8 @@ EXPORTS = [
     "aceapex_range_plan_workspace", "aceapex_range_plan_last", "aceapex_decode_ranges", "aceapex_decode_range",
 ]
 OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH, OPT_ROUND0_TILE = 1, 2, 3, 4, 5, 6
+OPT_TAIL_MODE, OPT_JUMP_PASSES = 7, 8
+TAIL_JUMP, TAIL_CHASE = 0, 1
 
 
 class AceapexError(RuntimeError):
@@ -90,7 +92,7 @@ def _load():
     L.aceapex_decoder_info.argtypes = [vp, P(Info)]
     L.aceapex_decoder_workspace.argtypes = [vp, P(u64)]
     L.aceapex_decode_all.argtypes = [vp, vp, u64, vp, u64, ctypes.c_int, vp]
-    L.aceapex_decoder_stage_ms.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float)]
+    L.aceapex_decoder_stage_ms.argtypes = [vp] + [P(ctypes.c_float)] * 4
     L.aceapex_decoder_set_timing.argtypes = [vp, ctypes.c_int]
     L.aceapex_decoder_status.argtypes = [vp, vp, vp, P(ctypes.c_int32), P(u64)]
     L.aceapex_decoder_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
@@ -101,7 +103,7 @@ def _load():
     L.aceapex_batch_workspace.argtypes = [vp, P(u64)]
     L.aceapex_batch_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
     L.aceapex_batch_set_timing.argtypes = [vp, ctypes.c_int]
-    L.aceapex_batch_stage_ms.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float)]
+    L.aceapex_batch_stage_ms.argtypes = [vp] + [P(ctypes.c_float)] * 4
     L.aceapex_decode_batch.argtypes = [vp, vp, u64, ctypes.c_int, vp]
     u64p = P(u64)
     L.aceapex_decoder_build_index.argtypes = [vp, vp, vp, u64, vp]
@@ -263,11 +265,13 @@ class Decoder:
                                               ctypes.byref(nt), threads), "closure_blocks")
         return blocks[: nb.value], nt.value, nb.value
 
-    def stage_ms(self):
-        a, p, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
-        _check(_load().aceapex_decoder_stage_ms(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(c)),
-               "stage_ms")
-        return a.value, p.value, c.value
+    def stage_ms(self, remainder=False):
+        """(entropy, parse, copy) ms of the last timed decode, summed over
+        windows; remainder=True appends the copy's deep-remainder part."""
+        a, p, c, r = ctypes.c_float(), ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        _check(_load().aceapex_decoder_stage_ms(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(c),
+                                                ctypes.byref(r)), "stage_ms")
+        return (a.value, p.value, c.value, r.value) if remainder else (a.value, p.value, c.value)
 
 
 def workspace_status(work, stream=None):
@@ -318,11 +322,11 @@ class Batch:
     def set_timing(self, on=True):
         _check(_load().aceapex_batch_set_timing(self._h, int(bool(on))), "batch_set_timing")
 
-    def stage_ms(self):
-        a, p, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
-        _check(_load().aceapex_batch_stage_ms(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(c)),
-               "batch_stage_ms")
-        return a.value, p.value, c.value
+    def stage_ms(self, remainder=False):
+        a, p, c, r = ctypes.c_float(), ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        _check(_load().aceapex_batch_stage_ms(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(c),
+                                              ctypes.byref(r)), "batch_stage_ms")
+        return (a.value, p.value, c.value, r.value) if remainder else (a.value, p.value, c.value)
 
     def decode(self, copy_mode=COPY_PERIODIC, stream=None, work=None):
         w = self.workspace() if work is None else work

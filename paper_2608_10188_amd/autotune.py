@@ -7,15 +7,17 @@ fastest.  Runs on the device; the caller supplies outputs to compare.
 """
 import itertools
 
-from . import OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_GRAPH, OPT_ROUND0_TILE, OPT_TAIL_CHUNKS
+from . import (OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_GRAPH, OPT_ROUND0_TILE, OPT_TAIL_CHUNKS,
+               OPT_TAIL_MODE)
 
-DEFAULT = {OPT_BULK_ROUNDS: 4, OPT_FILL_ROUNDS: 0, OPT_FILL_TAIL: 0, OPT_TAIL_CHUNKS: 1, OPT_ROUND0_TILE: 1, OPT_GRAPH: 1}
+DEFAULT = {OPT_BULK_ROUNDS: 4, OPT_FILL_ROUNDS: 0, OPT_FILL_TAIL: 0, OPT_TAIL_CHUNKS: 1, OPT_ROUND0_TILE: 1,
+           OPT_TAIL_MODE: 0, OPT_GRAPH: 1}
 
 GRID = {
     OPT_BULK_ROUNDS: [1, 2, 4, 8],
     OPT_FILL_ROUNDS: [0, 1],
-    OPT_FILL_TAIL: [0, 1],
     OPT_ROUND0_TILE: [1, 0],
+    OPT_TAIL_MODE: [0, 1],
 }
 
 

@@ -53,7 +53,6 @@ __device__ inline AX_GLOBAL T* gp(T* p) {
 }
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef u32x4 u32x4_u __attribute__((aligned(1)));  // 16 bytes at any byte address (one dwordx4 load)
-typedef u32x4 u32x4_u __attribute__((aligned(1)));  // 16 bytes at any byte address (one dwordx4 load)
 
 constexpr uint32_t kMaxB = 16384;           // largest block the device path decodes
 constexpr uint32_t kParseThreads = 256;
@@ -65,6 +64,9 @@ constexpr uint8_t kPending = 0xFF;          // done[] value of a token not yet c
 constexpr uint32_t kSub = 64;               // pending-list sublists (one counter each, 256 B apart)
 constexpr uint32_t kCounterStride = 64;     // u32 between two sublist counters
 constexpr uint32_t kMaxRoundGrid = 4096;    // workgroups of a round launch
+// last round: list the leftovers (persistent launch) or mark them for
+// pointer jumping (first entries and leftover-map bits)
+constexpr int kMarkList = 1, kMarkJump = 2;
 
 struct DevStatus {
   int32_t err;
@@ -72,8 +74,11 @@ struct DevStatus {
   unsigned long long bad_block;
   uint32_t ticket;
   uint32_t long_count;
-  uint32_t n_pending;  // tokens left for the persistent finish
-  uint32_t pad1[57];
+  uint32_t n_pending;  // tokens the bulk rounds left (the deep remainder)
+  uint32_t pad2;
+  uint32_t jump_used;    // jump passes that found active entries (0: all of them did)
+  uint32_t n_jwords;     // leftover-map words with bits set (the jump kernels' work list)
+  uint32_t pad1[54];
 };
 static_assert(sizeof(DevStatus) == 256, "status block is 256 bytes");
 
@@ -805,11 +810,14 @@ struct CopyArgs {
   DevStatus* st;
   uint32_t* pbits;           // the last round's leftovers, one bit per token
   const uint32_t* plist;     // the same tokens, ascending (the persistent finish's work)
-  int mark;                  // this round is the last: mark leftovers in pbits
+  int mark;                  // this round is the last: 0 no, else kMarkList or kMarkJump
   uint64_t spin_limit;
   int serial;
   int fill_round, fill_tail;  // later rounds / persistent launch: kFillLaneWave or kFillSegmented
   uint32_t tail_chunks;       // consecutive 64-token chunks per persistent-launch ticket
+  uint32_t* J;                // pointer jumping: one entry per window position
+  uint64_t* lmap;             // pointer jumping: leftover map
+  uint32_t S;                 // position stride of a window block
 };
 
 __device__ inline void token_at(const uint64_t* tok, uint64_t t, uint64_t& src, uint64_t& dst, uint32_t& len) {
@@ -1027,6 +1035,143 @@ __device__ inline uint32_t xcd_item(uint32_t g, uint32_t n) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
 }
 
+// ------------------------------------------------ marking for pointer jumping --
+//
+// In the last bulk round, the tokens still pending (the deep remainder) are
+// marked for pointer jumping (see the jump kernels below): every byte of a
+// pending token gets its first entry in the jump array — its source position
+// src + (k mod dist) by window position (byte o of window block x is
+// x * S + o), or the source's value when the source's block is not in the
+// window (the byte is final) — and its bit in the leftover map.  A wave lays
+// its lanes' pending tokens end to end and takes eight bytes per lane.
+constexpr uint32_t kJRes = 0x80000000u;  // entry holds a final byte value (low 8 bits)
+constexpr uint32_t kJMarkBytes = 8;
+constexpr uint32_t kJLongMark = 256;     // pending tokens at least this long are marked by a workgroup each
+
+struct MarkStage {
+  uint32_t end[64];  // inclusive prefix of pending lengths
+  uint32_t item[64];
+  uint64_t src[64], dst[64];
+};
+
+// Window position of the first byte of archive block qb of the job of
+// window block wb, or false when that block is not in this window (its bytes
+// are final: an earlier window wrote them, or the plan does not decode
+// them).
+__device__ inline bool window_block(const WinBlock* wbl, uint32_t S, const WinBlock& wb, uint64_t qb, uint32_t& wq) {
+  const uint64_t b0 = wbl[wb.first].b;
+  uint32_t x;
+  if (qb >= b0 && qb - b0 < wb.count && wbl[wb.first + uint32_t(qb - b0)].b == qb) {
+    x = wb.first + uint32_t(qb - b0);  // the job's blocks are consecutive up to qb (whole-archive windows)
+  } else {
+    uint32_t lo = wb.first, hi = wb.first + wb.count;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (wbl[mid].b < qb) lo = mid + 1; else hi = mid;
+    }
+    if (lo == wb.first + wb.count || wbl[lo].b != qb) return false;
+    x = lo;
+  }
+  wq = x * S;
+  return true;
+}
+
+// Mark this wave's pending tokens (one per lane: `pend`, token t).  `row`:
+// when not null, every token lies in window block `row_item` and its bits go
+// to that block's LDS row (32-bit words); else to the leftover map with
+// global atomics.
+__device__ void mark_wave(const CopyArgs& a, bool pend, uint32_t t, MarkStage& ms, uint32_t* row,
+                          uint32_t row_item) {
+  const uint32_t lane = lane_id();
+  uint64_t src = 0, dst = 0;
+  uint32_t len = 0;
+  if (pend) token_at(a.tok, t, src, dst, len);
+  // long tokens of a round over the leftover list are marked by a wave each
+  // (k_jmarklong): one wave laying out several would hold up the whole
+  // launch (a round-0 workgroup marks at most its own block).  They go to the round's
+  // output sublists, which the last round does not otherwise use: token t to
+  // sublist (t / 64) mod kSub, so a sublist holds at most ceil(T / 64 / kSub)
+  // * 64 of them, and its counter is one of kSub addresses 256 B apart
+  const bool lng = pend && len >= kJLongMark && !row;  // a block's own row bounds its work
+  if (lng) {
+    const uint32_t sub = (t >> 6) % kSub;
+    const uint32_t at = atomicAdd(a.cnt_out + sub * kCounterStride, 1u);
+    a.list_out[uint64_t(sub) * a.sub_cap + at] = t;
+  }
+  if (!pend || lng) len = 0;
+  uint32_t total;
+  const uint32_t ex = wave_excl_sum(len, &total);
+  if (!total) return;
+  ms.end[lane] = ex + len;
+  ms.item[lane] = pend ? a.tblk[t] : 0u;
+  ms.src[lane] = src;
+  ms.dst[lane] = dst;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  AX_GLOBAL uint32_t* const J = gp(a.J);
+  uint32_t* const lm32 = reinterpret_cast<uint32_t*>(a.lmap);
+  for (uint32_t f0 = lane * kJMarkBytes; f0 < total; f0 += 64 * kJMarkBytes) {
+    uint32_t l = 0;  // first token whose prefix end exceeds f0
+#pragma unroll
+    for (uint32_t step = 32; step; step >>= 1)
+      if (ms.end[l + step - 1] <= f0) l += step;
+    uint32_t e = ms.end[l], item = ms.item[l];
+    WinBlock wb = a.wbl[item];
+    JobDev jd = a.jobs[wb.job];
+    uint64_t bs = wb.b * jd.B;
+    uint32_t lb = __builtin_ctz(jd.B);  // block sizes are powers of two
+    src = ms.src[l], dst = ms.dst[l];
+    uint32_t k = f0 - (l ? ms.end[l - 1] : 0u);
+    uint64_t dist = dst - src, j = dist > k ? k : uint64_t(k % uint32_t(dist));
+    // window position of the source block last looked up (sources of a run
+    // of bytes are consecutive: one lookup per block)
+    uint64_t cb = wb.b;
+    uint32_t cbase = item * a.S;
+    bool cin = true;
+    uint32_t mw = ~0u, mbits = 0;  // leftover-map word being gathered and its bits
+    for (uint32_t q = 0; q < kJMarkBytes && f0 + q < total; ++q) {
+      if (f0 + q >= e) {  // the next pending token
+        do { ++l; } while (ms.end[l] == e);
+        e = ms.end[l];
+        src = ms.src[l], dst = ms.dst[l];
+        if (ms.item[l] != item) {
+          item = ms.item[l];
+          wb = a.wbl[item];
+          jd = a.jobs[wb.job];
+          bs = wb.b * jd.B;
+          lb = __builtin_ctz(jd.B);
+        }
+        k = 0, j = 0, dist = dst - src;
+        cb = wb.b, cbase = item * a.S, cin = true;
+      }
+      const uint64_t sp = src + j;  // source position
+      const uint64_t sb = sp >> lb;
+      if (sb != cb) {
+        cb = sb;
+        cin = window_block(a.wbl, a.S, wb, sb, cbase);
+      }
+      const uint32_t v = cin ? cbase + uint32_t(sp & (jd.B - 1)) : kJRes | gp(jd.out)[sp];
+      const uint32_t d = item * a.S + uint32_t(dst - bs) + k;  // this byte's window position
+      J[d] = v;
+      if ((d >> 5) != mw) {
+        if (mbits) {
+          if (row) atomicOr(&row[mw - row_item * (a.S / 32)], mbits);
+          else atomicOr(&lm32[mw], mbits);
+        }
+        mw = d >> 5, mbits = 0;
+      }
+      mbits |= 1u << (d & 31);
+      ++k;
+      if (++j == dist) j = 0;
+    }
+    if (mbits) {
+      if (row) atomicOr(&row[mw - row_item * (a.S / 32)], mbits);
+      else atomicOr(&lm32[mw], mbits);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();  // the stage is read before the caller's next use
+}
+
 // Level-synchronous rounds.  A token copied in round r marks done = r; a
 // token is ready in round r only if its covering tokens are marked < r, i.e.
 // were copied by an earlier launch, so no access within a round races.
@@ -1047,6 +1192,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t tile[kMaxB];
   __shared__ uint32_t dirty[kMaxB / 16 / 32];  // chunks of the tile that receive match bytes
   __shared__ uint32_t rdy[kMaxB / 32];         // the block's tokens filled here (min_match >= 1)
+  __shared__ uint32_t lft[kMaxB / 32];         // the block's tokens left pending (marked for jumping)
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const uint32_t lane = lane_id(), item = xcd_item(blockIdx.x, gridDim.x);
   if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
@@ -1061,7 +1207,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   const uint32_t ntb = t1 - wb.tok;  // <= blen: tokens are at least a byte long
   // the serial ablation reads in-block sources back from the tile: load all of it
   for (uint32_t k = threadIdx.x; k < kMaxB / 16 / 32; k += kCopyThreads) dirty[k] = a.serial ? ~0u : 0u;
-  for (uint32_t k = threadIdx.x; k < (ntb + 31) / 32; k += kCopyThreads) rdy[k] = 0;
+  for (uint32_t k = threadIdx.x; k < (ntb + 31) / 32; k += kCopyThreads) rdy[k] = lft[k] = 0;
   __syncthreads();
   for (uint32_t base = wb.tok; base < t1; base += kCopyThreads) {
     const uint32_t t = base + threadIdx.x;
@@ -1095,8 +1241,9 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       }
     }
     const bool left = act && !ready;
-    if (a.mark) {  // the only round: mark the leftovers for the persistent launch
-      if (left) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+    if (a.mark) {  // the only round: leftovers stay pending (listed, or marked after the fills)
+      if (left && a.mark == kMarkList) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+      if (left && a.mark == kMarkJump) atomicOr(&lft[(t - wb.tok) >> 5], 1u << ((t - wb.tok) & 31));
       continue;
     }
     // a wave's tokens fall in at most two 64-token groups, hence two sublists
@@ -1191,6 +1338,23 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       for (uint32_t i = 16 * k; i < blen; ++i) out[bs + i] = tile[i];
     }
   }
+  if (a.mark != kMarkJump) return;
+  // the block's pending tokens, marked for pointer jumping: the tile's bytes
+  // now hold the block's leftover-map row and the waves' stages
+  __syncthreads();
+  uint32_t* const row = reinterpret_cast<uint32_t*>(tile);
+  MarkStage* const mst = reinterpret_cast<MarkStage*>(tile + kMaxB / 8);
+  static_assert(kMaxB / 8 + (kCopyThreads / 64) * sizeof(MarkStage) <= kMaxB, "marking fits the tile");
+  for (uint32_t k = threadIdx.x; k < a.S / 32; k += kCopyThreads) row[k] = 0;
+  __syncthreads();
+  for (uint32_t base = wb.tok; base < t1; base += kCopyThreads) {
+    const uint32_t t = base + threadIdx.x, r = t - wb.tok;
+    const bool pend = t < t1 && ((lft[r >> 5] >> (r & 31)) & 1);
+    mark_wave(a, pend, t, mst[threadIdx.x >> 6], row, item);
+  }
+  __syncthreads();
+  uint32_t* const lm = reinterpret_cast<uint32_t*>(a.lmap) + uint64_t(item) * (a.S / 32);
+  for (uint32_t k = threadIdx.x; k < a.S / 32; k += kCopyThreads) lm[k] = row[k];
 }
 
 // Round 0 as a flat grid over the window's tokens (the alternative
@@ -1201,6 +1365,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
 // group and so in one sublist.
 __global__ __launch_bounds__(kCopyThreads) void k_round0_waves(CopyArgs a) {
   __shared__ FillStage stage[kCopyThreads / 64];
+  __shared__ MarkStage mstage[kCopyThreads / 64];
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const uint32_t lane = lane_id();
   FillStage& fs = stage[threadIdx.x >> 6];
@@ -1234,7 +1399,8 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0_waves(CopyArgs a) {
     if (ready && !split) a.done[t] = 0;
     const bool left = act && !ready;
     if (a.mark) {
-      if (left) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+      if (left && a.mark == kMarkList) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+      if (a.mark == kMarkJump) mark_wave(a, left, t, mstage[threadIdx.x >> 6], nullptr, 0);
       continue;
     }
     const uint64_t m = __ballot(left);
@@ -1253,6 +1419,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0_waves(CopyArgs a) {
 // round, to the bitmap of the persistent launch.
 __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
   __shared__ FillStage stage[kCopyThreads / 64];
+  __shared__ MarkStage mstage[kCopyThreads / 64];
   __shared__ uint32_t sub_end[kSub];  // inclusive prefix of the input sublist lengths
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const uint32_t lane = lane_id();
@@ -1293,7 +1460,8 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     if (ready) a.done[t] = uint8_t(a.round);
     const bool left = act && !ready;
     if (a.mark) {
-      if (left) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+      if (left && a.mark == kMarkList) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
+      if (a.mark == kMarkJump) mark_wave(a, left, t, mstage[threadIdx.x >> 6], nullptr, 0);
       continue;
     }
     const uint64_t m = __ballot(left);
@@ -1435,14 +1603,17 @@ __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
       }
       uint64_t spins = 0;
       while (__ballot(pending)) {
+        // flags are read relaxed; an agent-scope acquire fence after a flag
+        // that reads a producer's store synchronises with the producer's
+        // agent-scope release fence before that store, so the bytes it
+        // filled are visible to the loads after the fence, on any XCD
         bool ready = pending;
         for (uint32_t i = 0; i < cnt && ready; ++i)
           ready = __hip_atomic_load(a.done + lo + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kPending;
         if (__ballot(ready)) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           fill_ready<true>(out, ready, dst, src, len, a.serial, a.fill_tail, fs);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-          __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the bytes are out before the flags
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           if (ready) __hip_atomic_store(a.done + t, uint8_t(a.round), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           pending = pending && !ready;
         } else {
@@ -1456,6 +1627,392 @@ __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
       }
     }
   }
+}
+
+// ------------------------------------------- deep remainder: pointer jumping --
+//
+// The tokens the bulk rounds leave pending (the deep remainder) are resolved
+// by pointer jumping over their bytes rather than by a chase of one
+// dependency hop at a time.  Positions are window-relative: byte o of window
+// block x is x * S + o (S = the largest block size of the plan), so every
+// byte of every archive block the window holds has a place in one array of
+// 32-bit entries (the jump array) and one bit in each of two bitmaps: the
+// leftover map (bytes written by pending tokens) and the active map
+// (leftover bytes whose value is not known yet).  An entry holds either the
+// window position its value comes from or, with kJRes set, the final byte
+// value.  Byte k of a pending token (dst, src, len) takes its value from
+// position src + (k mod dist), which lies below dst: a final byte (a
+// literal, a token a round copied, a byte of an earlier window or of a block
+// the plan does not decode) or a byte of another, earlier pending token.
+// Entries therefore form a forest rooted at final values.  A pass replaces
+// each active entry by the entry its entry names, twice over (three times
+// the hops per pass), so about log3(chain length) passes resolve every
+// chain; a gather then writes the leftover bytes as whole 16-byte chunks.
+// Updating entries in place is safe in any order: an entry always names a
+// byte holding the same value, and every read returns some complete entry.
+constexpr uint32_t kJPasses = 32;        // pass-flag slots
+constexpr uint32_t kJShards = 16;        // flag words per pass (workgroup g writes g mod 16)
+constexpr uint32_t kJFlagStride = 16;    // u32 between two flag words
+constexpr uint32_t kJMaxGrid = 8192;     // workgroups of a position-driven launch
+constexpr uint32_t kJChaseLimit = 1u << 24;  // hops the gather follows before it reports a device error
+
+struct JumpArgs {
+  const JobDev* jobs;
+  const WinBlock* wbl;
+  uint32_t n_items;    // window blocks
+  uint32_t n_tok;      // window tokens
+  uint32_t S;          // position stride of a window block
+  const uint64_t* tok;
+  const uint32_t* tblk;
+  const uint8_t* done;
+  uint32_t* J;         // one entry per window position
+  uint64_t* lmap;      // leftover map, one bit per window position
+  uint64_t* amap;      // active map
+  uint32_t* flags;     // kJPasses x kJShards words, kJFlagStride apart
+  uint8_t** ibase;     // per window block: where its output bytes start
+  uint32_t s_log2;     // log2 S
+  const uint32_t* llist;  // long pending tokens: kSub sublists of sub_cap
+  const uint32_t* lcnt;   // their counters, kCounterStride apart
+  uint32_t sub_cap;
+  uint32_t* wlist;     // leftover-map words with bits set, ascending
+  uint32_t* wpsum;     // per list-build workgroup: its words with bits set
+  DevStatus* st;
+  uint32_t pass;
+};
+
+__device__ inline bool jump_failed(const DevStatus* st) {
+  return __hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// An entry naming no leftover byte (cannot happen for entries the init
+// wrote): the decode reports a device error instead of following it.
+// `where` (recorded as the failing block, with the top bit set) names the
+// check: 1 settling the first entries, 2 a pass, 3 the gather.
+__device__ inline uint32_t jump_broken(DevStatus* st, uint32_t where) {
+  report(st, AX_E_DEVICE, (1ull << 63) | where);
+  return kJRes;
+}
+
+// Before the bulk rounds: the leftover map starts empty (the last round sets
+// its bits) and every window block records where its output bytes start.
+__global__ __launch_bounds__(kCopyThreads) void k_jprep(JumpArgs a) {
+  const uint64_t words = uint64_t(a.n_items) * (a.S / 64);
+  for (uint64_t g = uint64_t(blockIdx.x) * kCopyThreads + threadIdx.x; g < words;
+       g += uint64_t(gridDim.x) * kCopyThreads)
+    a.lmap[g] = 0;
+  for (uint32_t x = blockIdx.x * kCopyThreads + threadIdx.x; x < a.n_items; x += gridDim.x * kCopyThreads) {
+    const WinBlock wb = a.wbl[x];
+    const JobDev& jd = a.jobs[wb.job];
+    a.ibase[x] = jd.out + wb.b * jd.B;
+  }
+}
+
+// Long pending tokens: one wave per token, eight bytes per lane (first
+// entries as in the marking of a round, bits by global atomics).
+__global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
+  __shared__ uint32_t sub_end[kSub];  // inclusive prefix of the sublist lengths
+  if (jump_failed(a.st)) return;
+  if (threadIdx.x < 64) {
+    uint32_t tot;
+    const uint32_t c = a.lcnt[threadIdx.x * kCounterStride];
+    sub_end[threadIdx.x] = wave_excl_sum(c, &tot) + c;
+  }
+  __syncthreads();
+  const uint32_t n = sub_end[kSub - 1], lane = lane_id();
+  AX_GLOBAL uint32_t* const J = gp(a.J);
+  uint32_t* const lm32 = reinterpret_cast<uint32_t*>(a.lmap);
+  const uint32_t waves = gridDim.x * (kCopyThreads / 64);
+  for (uint32_t i = blockIdx.x * (kCopyThreads / 64) + (threadIdx.x >> 6); i < n; i += waves) {
+    uint32_t sl = 0;  // sublist holding item i
+#pragma unroll
+    for (uint32_t step = 32; step; step >>= 1)
+      if (sub_end[sl + step - 1] <= i) sl += step;
+    const uint32_t start = sl ? sub_end[sl - 1] : 0u;
+    const uint32_t t = a.llist[uint64_t(sl) * a.sub_cap + (i - start)];
+    uint64_t src, dst;
+    uint32_t len;
+    token_at(a.tok, t, src, dst, len);
+    const uint32_t item = a.tblk[t];
+    const WinBlock wb = a.wbl[item];
+    const JobDev jd = a.jobs[wb.job];
+    const uint32_t lb = __builtin_ctz(jd.B);
+    const uint64_t bs = wb.b << lb, dist = dst - src;
+    for (uint32_t k0 = lane * kJMarkBytes; k0 < len; k0 += 64 * kJMarkBytes) {
+      uint64_t j = dist > k0 ? k0 : uint64_t(k0 % uint32_t(dist));
+      uint64_t cb = ~0ull;
+      uint32_t cbase = 0;
+      bool cin = false;
+      uint32_t mw = ~0u, mbits = 0;
+      for (uint32_t k = k0; k < k0 + kJMarkBytes && k < len; ++k) {
+        const uint64_t sp = src + j, sb = sp >> lb;
+        if (sb != cb) cb = sb, cin = window_block(a.wbl, a.S, wb, sb, cbase);
+        const uint32_t v = cin ? cbase + uint32_t(sp & (jd.B - 1)) : kJRes | gp(jd.out)[sp];
+        const uint32_t d = item * a.S + uint32_t(dst - bs) + k;
+        J[d] = v;
+        if ((d >> 5) != mw) {
+          if (mbits) atomicOr(&lm32[mw], mbits);
+          mw = d >> 5, mbits = 0;
+        }
+        mbits |= 1u << (d & 31);
+        if (++j == dist) j = 0;
+      }
+      if (mbits) atomicOr(&lm32[mw], mbits);
+    }
+  }
+}
+
+constexpr uint32_t kJDense = 0xFFFFFFFFu;  // n_jwords: the map is walked whole (dense)
+
+// The work list: the leftover-map words with bits set, ascending (two
+// launches: counts per workgroup of kJListWords words, then the scatter).
+constexpr uint32_t kJListWords = 16 * kCopyThreads;
+__global__ __launch_bounds__(kCopyThreads) void k_jlcount(JumpArgs a) {
+  __shared__ uint32_t red[kCopyThreads / 64];
+  if (jump_failed(a.st)) return;
+  const uint64_t words = uint64_t(a.n_items) * (a.S / 64), w0 = uint64_t(blockIdx.x) * kJListWords;
+  uint32_t c = 0;
+  for (uint32_t k = threadIdx.x; k < kJListWords; k += kCopyThreads)
+    if (w0 + k < words) c += a.lmap[w0 + k] != 0;
+  c = block_sum_u32(c, red);
+  if (threadIdx.x == 0) a.wpsum[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kCopyThreads) void k_jlist(JumpArgs a) {
+  __shared__ uint32_t red[kCopyThreads / 64];
+  __shared__ uint32_t wtot[kCopyThreads / 64];
+  if (jump_failed(a.st)) return;
+  const uint64_t words = uint64_t(a.n_items) * (a.S / 64), w0 = uint64_t(blockIdx.x) * kJListWords;
+  uint32_t before = 0, all = 0;
+  for (uint32_t g = threadIdx.x; g < gridDim.x; g += kCopyThreads) {
+    const uint32_t c = a.wpsum[g];
+    if (g < blockIdx.x) before += c;
+    all += c;
+  }
+  const uint32_t base = block_sum_u32(before, red);
+  const uint32_t busy = block_sum_u32(all, red);
+  if (uint64_t(busy) * 4 > words) {  // dense: the kernels walk the whole map
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->n_jwords = kJDense;
+    return;
+  }
+  constexpr uint32_t kPer = kJListWords / kCopyThreads;  // consecutive words per thread
+  uint32_t bits = 0, c = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint64_t g = w0 + kPer * threadIdx.x + q;
+    if (g < words && a.lmap[g] != 0) bits |= 1u << q, ++c;
+  }
+  uint32_t tot;
+  const uint32_t ex = wave_excl_sum(c, &tot);
+  if (lane_id() == 0) wtot[threadIdx.x >> 6] = tot;
+  __syncthreads();
+  uint32_t at = base + ex;
+  for (uint32_t k = 0; k < (threadIdx.x >> 6); ++k) at += wtot[k];
+  while (bits) {
+    const uint32_t q = __builtin_ctz(bits);
+    bits &= bits - 1;
+    a.wlist[at++] = uint32_t(w0 + kPer * threadIdx.x + q);
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kCopyThreads - 1) a.st->n_jwords = at;
+}
+
+// The position-driven kernels below visit the leftover-map words with bits
+// set, eight at a time, one position per lane, so the map's rows are read
+// and written as coalesced 256-byte rows.  Two walks, chosen per window by
+// the list build: when more than a quarter of the map's words are busy, a
+// wave reads 64 map words per step (four 16-word chunks a grid apart, so a
+// dense region spreads over many waves) and takes the busy ones eight at a
+// time; otherwise the work list is walked eight words per step (the next
+// step's words in flight), so a sparse map costs no empty reads.
+constexpr uint32_t kJStepWords = 8;
+constexpr uint32_t kJChunk = 16;
+
+// A group of up to kJStepWords busy map words: their indices and bits
+// (wave-uniform, held in scalar registers; bits 0 marks an unused slot).
+struct WordGroup {
+  uint32_t g[kJStepWords];
+  uint64_t wv[kJStepWords];
+};
+
+// (the builtin returns int: widen through uint32_t, not by sign extension)
+__device__ inline uint64_t uniform64(uint64_t v) {
+  return uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))))) |
+         (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))))) << 32);
+}
+
+// Call f(group) for groups of up to kJStepWords busy words of `map` (the
+// leftover or the active map).
+template <class F>
+__device__ inline void walk_words(const JumpArgs& a, const uint64_t* map, F&& f) {
+  const uint32_t lane = lane_id();
+  const uint64_t waves = uint64_t(gridDim.x) * (kCopyThreads / 64);
+  const uint64_t wave = uint64_t(blockIdx.x) * (kCopyThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t n = a.st->n_jwords;
+  WordGroup w;
+  if (n == kJDense) {
+    const uint64_t words = uint64_t(a.n_items) * (a.S / 64);
+    const uint64_t steps = (words + kJChunk * 4 * waves - 1) / (kJChunk * 4 * waves);
+    for (uint64_t i = 0; i < steps; ++i) {
+      // lane l reads word l mod 16 of chunk (4 i + l / 16) * waves + wave
+      const uint64_t mine = ((i * 4 + (lane >> 4)) * waves + wave) * kJChunk + (lane & 15u);
+      const uint64_t mw = mine < words ? map[mine] : 0ull;
+      uint64_t nz = uniform64(__ballot(mw != 0));
+      while (nz) {
+#pragma unroll
+        for (uint32_t u = 0; u < kJStepWords; ++u) {
+          w.g[u] = 0;
+          w.wv[u] = 0;
+          if (nz) {
+            const uint32_t wi = uint32_t(__builtin_ctzll(nz));
+            nz &= nz - 1;
+            w.wv[u] = uniform64(__shfl((unsigned long long)mw, int(wi), 64));
+            w.g[u] = uint32_t(((i * 4 + (wi >> 4)) * waves + wave) * kJChunk + (wi & 15u));
+          }
+        }
+        f(w);
+      }
+    }
+    return;
+  }
+  for (uint64_t i0 = wave * kJStepWords; i0 < n; i0 += waves * kJStepWords) {
+#pragma unroll
+    for (uint32_t u = 0; u < kJStepWords; ++u) {
+      w.g[u] = i0 + u < n ? a.wlist[i0 + u] : 0u;
+      w.wv[u] = i0 + u < n ? map[w.g[u]] : 0ull;
+    }
+    f(w);
+  }
+}
+
+// Value of the byte at window position v (a final byte).
+__device__ inline uint32_t jbyte(const JumpArgs& a, uint32_t v) {
+  return gp(a.ibase[v >> a.s_log2])[v & ((1u << a.s_log2) - 1u)];
+}
+
+// First entries, settled: an entry naming a position outside the leftover
+// map (a final byte) takes that byte's value; the rest stay active.
+__global__ __launch_bounds__(kCopyThreads) void k_jinit(JumpArgs a) {
+  if (jump_failed(a.st)) return;
+  const uint32_t lane = lane_id(), limit = a.n_items * a.S;
+  AX_GLOBAL uint32_t* const J = gp(a.J);
+  walk_words(a, a.lmap, [&](const WordGroup& w) __attribute__((always_inline)) {
+    const uint32_t* const g = w.g;
+    const uint64_t* const wv = w.wv;
+    uint32_t v[kJStepWords];
+#pragma unroll
+    for (uint32_t u = 0; u < kJStepWords; ++u) v[u] = ((wv[u] >> lane) & 1) ? J[g[u] * 64 + lane] : kJRes;
+    bool leftover[kJStepWords];
+#pragma unroll
+    for (uint32_t u = 0; u < kJStepWords; ++u) {
+      leftover[u] = true;
+      if (!(v[u] & kJRes)) {
+        if (v[u] >= limit) v[u] = jump_broken(a.st, 1);
+        else leftover[u] = (a.lmap[v[u] >> 6] >> (v[u] & 63)) & 1;
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kJStepWords; ++u)
+      if (!leftover[u]) v[u] = kJRes | jbyte(a, v[u]);
+#pragma unroll
+    for (uint32_t u = 0; u < kJStepWords; ++u) {
+      if (!wv[u]) continue;
+      const bool act = (wv[u] >> lane) & 1;
+      if (act && !leftover[u]) J[g[u] * 64 + lane] = v[u];
+      const uint64_t still = __ballot(act && !(v[u] & kJRes));
+      if (lane == 0) a.amap[g[u]] = still;
+    }
+  });
+  // the dense walk visits only busy words: the others' active bits are zero
+  if (a.st->n_jwords == kJDense) {
+    const uint64_t words = uint64_t(a.n_items) * (a.S / 64);
+    for (uint64_t w = uint64_t(blockIdx.x) * kCopyThreads + threadIdx.x; w < words;
+         w += uint64_t(gridDim.x) * kCopyThreads)
+      if (!a.lmap[w]) a.amap[w] = 0;
+  }
+}
+
+// One jump pass: every active entry takes the entry two steps along its
+// chain.  A pass whose predecessor left nothing active exits at once (and
+// the first such pass records how many passes did work).
+__global__ __launch_bounds__(kCopyThreads) void k_jpass(JumpArgs a) {
+  if (jump_failed(a.st)) return;
+  if (a.pass > 0) {
+    const uint32_t* pf = a.flags + (a.pass - 1) * kJShards * kJFlagStride;
+    const uint32_t f = threadIdx.x < kJShards ? pf[threadIdx.x * kJFlagStride] : 0u;
+    if (!__syncthreads_or(int(f))) {
+      if (blockIdx.x == 0 && threadIdx.x == 0 && a.st->jump_used == 0) a.st->jump_used = a.pass;
+      return;
+    }
+  }
+  const uint32_t lane = lane_id(), limit = a.n_items * a.S;
+  AX_GLOBAL uint32_t* const J = gp(a.J);
+  bool any = false;
+  walk_words(a, a.amap, [&](const WordGroup& w) __attribute__((always_inline)) {
+    const uint32_t* const g = w.g;
+    const uint64_t* const wv = w.wv;
+    uint32_t v[kJStepWords];
+#pragma unroll
+    for (uint32_t u = 0; u < kJStepWords; ++u) v[u] = ((wv[u] >> lane) & 1) ? J[g[u] * 64 + lane] : kJRes;
+#pragma unroll
+    for (uint32_t u = 0; u < kJStepWords; ++u)
+      if (!(v[u] & kJRes)) v[u] = v[u] < limit ? J[v[u]] : jump_broken(a.st, 2);
+#pragma unroll
+    for (uint32_t u = 0; u < kJStepWords; ++u)
+      if (!(v[u] & kJRes)) v[u] = v[u] < limit ? J[v[u]] : jump_broken(a.st, 2);
+#pragma unroll
+    for (uint32_t u = 0; u < kJStepWords; ++u) {
+      if (!wv[u]) continue;
+      const bool act = (wv[u] >> lane) & 1;
+      if (act) J[g[u] * 64 + lane] = v[u];
+      const uint64_t still = __ballot(act && !(v[u] & kJRes));
+      if (lane == 0 && still != wv[u]) a.amap[g[u]] = still;
+      any |= still != 0;
+    }
+  });
+  if (__syncthreads_or(int(any)) && threadIdx.x == 0)
+    a.flags[(a.pass * kJShards + blockIdx.x % kJShards) * kJFlagStride] = 1;
+}
+
+// Output: every leftover byte takes its entry's value (following any entry
+// the passes left unfinished).  Of a group of eight busy words, a lane owns
+// four consecutive positions of one word in each half: one 16-byte entry
+// load, then one 32-bit store when all four are leftover (byte stores
+// otherwise: the other bytes keep their value).
+__global__ __launch_bounds__(kCopyThreads) void k_jgather(JumpArgs a) {
+  if (jump_failed(a.st)) return;
+  const uint32_t lane = lane_id(), limit = a.n_items * a.S, omask = (1u << a.s_log2) - 1u;
+  const AX_GLOBAL uint32_t* const J = gp(a.J);
+  const uint32_t sub = lane >> 4, q4 = 4 * (lane & 15u);
+  walk_words(a, a.lmap, [&](const WordGroup& w) __attribute__((always_inline)) {
+#pragma unroll
+    for (uint32_t h = 0; h < 2; ++h) {
+      // this lane's word of the half: word 4 h + (lane / 16) (a select: it varies by lane)
+      const uint32_t g0 = w.g[4 * h], g1 = w.g[4 * h + 1], g2 = w.g[4 * h + 2], g3 = w.g[4 * h + 3];
+      const uint64_t w0 = w.wv[4 * h], w1 = w.wv[4 * h + 1], w2 = w.wv[4 * h + 2], w3 = w.wv[4 * h + 3];
+      const uint32_t gk = sub < 2 ? (sub == 0 ? g0 : g1) : (sub == 2 ? g2 : g3);
+      const uint64_t wk = sub < 2 ? (sub == 0 ? w0 : w1) : (sub == 2 ? w2 : w3);
+      const uint32_t bits4 = uint32_t(wk >> q4) & 0xFu;
+      if (!bits4) continue;
+      const uint32_t p = gk * 64 + q4;
+      u32x4 e = *reinterpret_cast<const AX_GLOBAL u32x4*>(J + p);
+      uint32_t x0 = (bits4 & 1) ? e.x : kJRes, x1 = (bits4 & 2) ? e.y : kJRes;
+      uint32_t x2 = (bits4 & 4) ? e.z : kJRes, x3 = (bits4 & 8) ? e.w : kJRes;
+      if (!(x0 & x1 & x2 & x3 & kJRes)) {  // an entry the passes did not finish: follow it
+        for (uint32_t hop = 0; !(x0 & kJRes); ++hop) x0 = x0 < limit && hop < kJChaseLimit ? J[x0] : jump_broken(a.st, 3);
+        for (uint32_t hop = 0; !(x1 & kJRes); ++hop) x1 = x1 < limit && hop < kJChaseLimit ? J[x1] : jump_broken(a.st, 3);
+        for (uint32_t hop = 0; !(x2 & kJRes); ++hop) x2 = x2 < limit && hop < kJChaseLimit ? J[x2] : jump_broken(a.st, 3);
+        for (uint32_t hop = 0; !(x3 & kJRes); ++hop) x3 = x3 < limit && hop < kJChaseLimit ? J[x3] : jump_broken(a.st, 3);
+      }
+      AX_GLOBAL uint8_t* const o = gp(a.ibase[p >> a.s_log2]) + (p & omask);
+      if (bits4 == 0xFu) {
+        *reinterpret_cast<AX_GLOBAL uint32_t*>(o) = (x0 & 0xFFu) | ((x1 & 0xFFu) << 8) | ((x2 & 0xFFu) << 16) | ((x3 & 0xFFu) << 24);
+      } else {
+        if (bits4 & 1) o[0] = uint8_t(x0);
+        if (bits4 & 2) o[1] = uint8_t(x1);
+        if (bits4 & 4) o[2] = uint8_t(x2);
+        if (bits4 & 8) o[3] = uint8_t(x3);
+      }
+    }
+  });
 }
 
 // Zero two word ranges (one launch for both).
@@ -1474,6 +2031,8 @@ __global__ void k_window_init(DevStatus* st, int first) {
     st->ticket = 0;
     st->long_count = 0;
     st->n_pending = 0;
+    st->jump_used = 0;
+    st->n_jwords = 0;
   }
 }
 
@@ -1486,8 +2045,9 @@ inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 namespace ax {
 
 struct Layout {
-  uint64_t status, nsym, lit, cmd, off, len, tok, tblk, cov, done, counts, list0, list1, llist, pbits, pcnt, plist,
-      total;
+  uint64_t status, nsym, lit, cmd, off, len, tok, tblk, cov, done, counts, jflags, list0, list1, llist, pbits, pcnt,
+      plist, lmap, amap, ibase, wlist, wpsum, total;
+  uint64_t jbytes;  // the jump array: the stream slots, dead once the parse is through
   uint64_t sub_cap;
 };
 
@@ -1518,7 +2078,20 @@ struct Plan {
   PlanOptions opt{};
   int copy_grid = 1;
   bool timing = false, events_ok = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t timed_windows = 0;  // windows the last timed decode recorded
+  // stage events, five per window: entropy, parse, bulk rounds, deep
+  // remainder, end
+  std::vector<hipEvent_t> ev;
+  // jump passes launched per window: from a bound on the chain length at
+  // first, then the count the device reported as needed (+1 spare pass,
+  // which exits at once and reports it again); the gather finishes any
+  // entry the passes leave, so the count never changes a byte
+  std::vector<uint32_t> jpass;
+  uint32_t* h_jused = nullptr;   // pinned: per window, passes that found work
+  size_t jused_cap = 0;
+  hipEvent_t jfed = nullptr;     // h_jused is complete after this
+  bool jfeed_pending = false, jsettled = false;
+  bool learn = true;             // plans rebuilt for every call (ranges) keep the bound
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
   void* graph_work = nullptr;
@@ -1528,12 +2101,16 @@ struct Plan {
     if (graph) (void)hipGraphExecDestroy(graph);
     if (graph_def) (void)hipGraphDestroy(graph_def);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
+    for (auto& e : ev) (void)hipEventDestroy(e);
     if (staged) {
       (void)hipEventSynchronize(staged);
       (void)hipEventDestroy(staged);
     }
+    if (jfed) {
+      (void)hipEventSynchronize(jfed);
+      (void)hipEventDestroy(jfed);
+    }
+    if (h_jused) (void)hipHostFree(h_jused);
     if (d_mem) (void)hipFree(d_mem);
     if (h_pinned) (void)hipHostFree(h_pinned);
     if (h_stage) (void)hipHostFree(h_stage);
@@ -1555,6 +2132,7 @@ static Layout make_layout(const Plan& P) {
   L.cov = at, at = align256(at + 8 * T);
   L.done = at, at = align256(at + T);
   L.counts = at, at = align256(at + 4ull * 3 * kSub * kCounterStride);
+  L.jflags = at, at = align256(at + 4ull * kJPasses * kJShards * kJFlagStride);  // cleared with the counters
   // a workgroup appends at most what it visits: ceil(T / kSub) plus one
   // launch-wide stride of slack per sublist
   L.sub_cap = (T + kSub - 1) / kSub + uint64_t(kCopyThreads) * ((kMaxRoundGrid + kSub - 1) / kSub + 1);
@@ -1564,13 +2142,31 @@ static Layout make_layout(const Plan& P) {
   L.pbits = at, at = align256(at + 4 * ((T + 31) / 32 + 64));
   L.pcnt = at, at = align256(at + 4 * ((T + 31) / 32 / kPackWords + 1));
   L.plist = at, at = align256(at + 4 * T);
+  L.lmap = at, at = align256(at + W * P.slot_b / 8);
+  L.ibase = at, at = align256(at + 8 * W);
+  L.wlist = at, at = align256(at + W * P.slot_b / 16);                        // one u32 per map word
+  L.wpsum = at, at = align256(at + 4 * (W * P.slot_b / 64 / kJListWords + 1));
+  L.amap = at, at = align256(at + W * P.slot_b / 8);
   L.total = at;
+  // the jump array (4 B per window position) reuses the four stream slots,
+  // dead once the parse is through: at least 5 B per window position
+  L.jbytes = L.len + W * P.len_cap - L.lit;
   return L;
 }
 
 static int hip_fail(hipError_t e, const char* what) {
   (void)what;
   return fail(AX_E_HIP, hipGetErrorString(e));
+}
+
+// Jump passes that resolve any chain of a window of `tok` tokens: a chain
+// visits each pending token at most once, the first entries span one hop,
+// and a pass triples the hops an entry spans.
+static uint32_t jump_pass_bound(uint64_t tok) {
+  uint32_t p = 1;
+  uint64_t span = 3;
+  while (p < kJPasses && span <= tok) ++p, span *= 3;
+  return p;
 }
 
 // Host tables of a plan: jobs, window blocks, windows, maxima.
@@ -1647,6 +2243,9 @@ static int build_tables(Plan* P, const std::vector<JobSpec>& specs) {
       }
     }
     close();
+    P->jpass.assign(P->wins.size(), 0);
+    for (size_t i = 0; i < P->wins.size(); ++i) P->jpass[i] = jump_pass_bound(P->wins[i].tok);
+    P->jsettled = false;
   } catch (const std::bad_alloc&) {
     return fail(AX_E_NOMEM, "plan tables");
   }
@@ -1721,8 +2320,10 @@ int plan_create(const std::vector<JobSpec>& specs, Plan** out) {
 }
 
 int plan_reset(Plan* P, const std::vector<JobSpec>& specs, hipStream_t s) {
-  // staging may still feed the previous upload
+  // staging may still feed the previous upload; a pass report of the old
+  // windows may still be on its way
   if (P->staged) (void)hipEventSynchronize(P->staged);
+  if (P->jfeed_pending) (void)hipEventSynchronize(P->jfed), P->jfeed_pending = false;
   int rc = build_tables(P, specs);
   if (!rc) rc = ensure_device(P);
   if (rc) return rc;
@@ -1758,6 +2359,7 @@ uint64_t plan_workspace_for(const aceapex_decoder* d, uint64_t max_blocks, uint6
 }
 
 void plan_copy_options(Plan* dst, const Plan* src) { dst->opt = src->opt; }
+void plan_set_learn(Plan* P, bool learn) { P->learn = learn; }
 
 int plan_parse_tokens(Plan* P, void* d_work, uint64_t work_len, hipStream_t s, uint64_t* src, uint64_t* dstlen) {
   if (work_len < P->lay.total) return fail(AX_E_CAPACITY, "workspace too small");
@@ -1843,6 +2445,14 @@ int plan_set_option(Plan* P, int option, int64_t value) {
       if (value < 0 || value > 1) return fail(AX_E_ARG, "graph must be 0 or 1");
       P->opt.graph = int(value);
       break;
+    case AX_OPT_TAIL_MODE:
+      if (value < 0 || value > 1) return fail(AX_E_ARG, "tail mode must be 0 or 1");
+      P->opt.tail_mode = int(value);
+      break;
+    case AX_OPT_JUMP_PASSES:
+      if (value < 0 || value > int64_t(kJPasses)) return fail(AX_E_ARG, "jump passes must be in [0, 32]");
+      P->opt.jump_passes = int(value);
+      break;
     default:
       return fail(AX_E_ARG, "unknown option");
   }
@@ -1861,68 +2471,107 @@ int plan_get_option(const Plan* P, int option, int64_t* value) {
     case AX_OPT_FILL_ROUNDS: *value = P->opt.fill_round; return AX_OK;
     case AX_OPT_FILL_TAIL: *value = P->opt.fill_tail; return AX_OK;
     case AX_OPT_GRAPH: *value = P->opt.graph; return AX_OK;
+    case AX_OPT_TAIL_MODE: *value = P->opt.tail_mode; return AX_OK;
+    case AX_OPT_JUMP_PASSES: *value = P->opt.jump_passes; return AX_OK;
     default: return fail(AX_E_ARG, "unknown option");
   }
 }
 
+// Stage events for every window of the plan (created when timing is on).
+static int ensure_events(Plan* P) {
+  const size_t need = 5 * P->wins.size();
+  while (P->ev.size() < need) {
+    hipEvent_t e;
+    hipError_t er = hipEventCreate(&e);
+    if (er != hipSuccess) return hip_fail(er, "hipEventCreate");
+    P->ev.push_back(e);
+  }
+  return AX_OK;
+}
+
 int plan_set_timing(Plan* P, int enable) {
   if (enable && !P->events_ok) {
-    for (auto& e : P->ev) {
-      hipError_t er = hipEventCreate(&e);
-      if (er != hipSuccess) return hip_fail(er, "hipEventCreate");
-    }
+    int rc = ensure_events(P);
+    if (rc) return rc;
     P->events_ok = true;
   }
   P->timing = enable != 0;
   return AX_OK;
 }
 
-int plan_stage_ms(Plan* P, float* ans, float* parse, float* copy) {
-  if (!P->events_ok) return fail(AX_E_ARG, "timing not enabled");
-  hipError_t e = hipEventSynchronize(P->ev[3]);
-  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-  (void)hipEventElapsedTime(ans, P->ev[0], P->ev[1]);
-  (void)hipEventElapsedTime(parse, P->ev[1], P->ev[2]);
-  (void)hipEventElapsedTime(copy, P->ev[2], P->ev[3]);
+int plan_stage_ms(Plan* P, float* ans, float* parse, float* copy, float* remainder) {
+  if (!P->events_ok || P->timed_windows == 0) return fail(AX_E_ARG, "timing not enabled");
+  float t[4] = {0, 0, 0, 0};
+  for (size_t wi = 0; wi < P->timed_windows; ++wi) {
+    hipEvent_t* e = P->ev.data() + 5 * wi;
+    hipError_t er = hipEventSynchronize(e[4]);
+    if (er != hipSuccess) return hip_fail(er, "hipEventSynchronize");
+    for (int k = 0; k < 4; ++k) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e[k], e[k + 1]);
+      t[k] += ms;
+    }
+  }
+  *ans = t[0];
+  *parse = t[1];
+  *copy = t[2] + t[3];
+  if (remainder) *remainder = t[3];
   return AX_OK;
 }
 
 // Enqueue the plan's kernels on s (also used inside a graph capture).
-static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool timed) {
+static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool timed, bool feedback) {
   const Layout& L = P->lay;
   DevStatus* st = reinterpret_cast<DevStatus*>(w + L.status);
   if (P->wins.empty()) hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st, 1);  // status only
   for (size_t wi = 0; wi < P->wins.size(); ++wi) {
     const Plan::Win& W = P->wins[wi];
-    const bool first = wi == 0, last = wi + 1 == P->wins.size();
+    const bool first = wi == 0;
     const WinBlock* wbl = P->d_wbl + W.at;
     hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st, int(first));
     uint32_t* counts = reinterpret_cast<uint32_t*>(w + L.counts);
     AnsArgs aa{P->d_jobs, wbl, W.items, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                P->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
-    if (timed && first) (void)hipEventRecord(P->ev[0], s);
+    hipEvent_t* ev = timed ? P->ev.data() + 5 * wi : nullptr;
+    if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_ans, dim3(4 * W.items), dim3(64), 0, s, aa);
-    if (timed && first) (void)hipEventRecord(P->ev[1], s);
+    if (ev) (void)hipEventRecord(ev[1], s);
     ParseArgs pa{P->d_jobs, wbl, W.items, W.tok, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                  P->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), reinterpret_cast<uint64_t*>(w + L.tok),
                  reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st};
     hipLaunchKernelGGL(k_parse, dim3(W.items), dim3(kParseThreads), 0, s, pa);
-    if (timed && first) (void)hipEventRecord(P->ev[2], s);
+    if (ev) (void)hipEventRecord(ev[2], s);
     const uint32_t ntok = W.tok;
+    const bool jump = P->opt.tail_mode == 0 && copy_mode != AX_COPY_SERIAL;
+    const int last_mark = jump ? kMarkJump : kMarkList;
     if (ntok) {
       uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(w + L.list0), reinterpret_cast<uint32_t*>(w + L.list1)};
       auto cset = [&](int r) { return counts + (r % 3) * kSub * kCounterStride; };
       const uint32_t n_words = (ntok + 31) / 32, pgrid = (n_words + kPackWords - 1) / kPackWords;
       // the list counters and the leftover bitmap start at zero
-      hipLaunchKernelGGL(k_clear2, dim3(pgrid), dim3(256), 0, s, counts, uint32_t(3 * kSub * kCounterStride),
+      hipLaunchKernelGGL(k_clear2, dim3(pgrid), dim3(256), 0, s, counts,
+                         uint32_t((L.jflags - L.counts) / 4 + kJPasses * kJShards * kJFlagStride),
                          reinterpret_cast<uint32_t*>(w + L.pbits), n_words);
       CopyArgs ca{P->d_jobs, wbl, W.items, reinterpret_cast<const uint64_t*>(w + L.tok),
                   reinterpret_cast<const uint32_t*>(w + L.tblk), ntok, reinterpret_cast<uint32_t*>(w + L.cov),
                   w + L.done, nullptr, lists[0], nullptr, cset(0), cset(1), uint32_t(L.sub_cap),
                   reinterpret_cast<uint32_t*>(w + L.llist), &st->long_count, 0, st,
                   reinterpret_cast<uint32_t*>(w + L.pbits), reinterpret_cast<const uint32_t*>(w + L.plist),
-                  P->opt.bulk_rounds <= 1, 1ull << 22, copy_mode == AX_COPY_SERIAL, P->opt.fill_round,
-                  P->opt.fill_tail, uint32_t(P->opt.tail_chunks)};
+                  P->opt.bulk_rounds <= 1 ? last_mark : 0, 1ull << 22, copy_mode == AX_COPY_SERIAL, P->opt.fill_round,
+                  P->opt.fill_tail, uint32_t(P->opt.tail_chunks), reinterpret_cast<uint32_t*>(w + L.lit),
+                  reinterpret_cast<uint64_t*>(w + L.lmap), P->slot_b};
+      // pointer jumping over window positions (the deep remainder); the
+      // jump array is the stream slots, dead once the parse is through
+      JumpArgs ja{P->d_jobs, wbl, W.items, ntok, P->slot_b, ca.tok, ca.tblk, ca.done,
+                  reinterpret_cast<uint32_t*>(w + L.lit), reinterpret_cast<uint64_t*>(w + L.lmap),
+                  reinterpret_cast<uint64_t*>(w + L.amap), reinterpret_cast<uint32_t*>(w + L.jflags),
+                  reinterpret_cast<uint8_t**>(w + L.ibase), uint32_t(__builtin_ctz(P->slot_b)),
+                  nullptr, nullptr, uint32_t(L.sub_cap), reinterpret_cast<uint32_t*>(w + L.wlist),
+                  reinterpret_cast<uint32_t*>(w + L.wpsum), st, 0};
+      const uint64_t mwords = uint64_t(W.items) * (P->slot_b / 64);  // leftover-map words
+      // eight listed words per wave step, four waves per workgroup
+      const uint32_t jgrid = uint32_t(std::min<uint64_t>((mwords + 31) / 32, kJMaxGrid));
+      if (jump) hipLaunchKernelGGL(k_jprep, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
       const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
       if (P->opt.round0_tile) hipLaunchKernelGGL(k_round0, dim3(W.items), dim3(kCopyThreads), 0, s, ca);
       else hipLaunchKernelGGL(k_round0_waves, dim3(grid), dim3(kCopyThreads), 0, s, ca);
@@ -1934,20 +2583,43 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
         ca.cnt_in = cset(r - 1);
         ca.cnt_out = cset(r);
         ca.cnt_clear = cset(r + 1);
-        ca.mark = r + 1 == P->opt.bulk_rounds;
+        ca.mark = r + 1 == P->opt.bulk_rounds ? last_mark : 0;
         // later rounds see the previous round's leftovers only
         hipLaunchKernelGGL(k_round, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       }
       ca.round = uint32_t(P->opt.bulk_rounds);
-      uint32_t* pcnt = reinterpret_cast<uint32_t*>(w + L.pcnt);
-      hipLaunchKernelGGL(k_pcount, dim3(pgrid), dim3(kCopyThreads), 0, s, ca.pbits, n_words, pcnt);
-      hipLaunchKernelGGL(k_pscatter, dim3(pgrid), dim3(kCopyThreads), 0, s, ca.pbits, n_words, pcnt,
-                         reinterpret_cast<uint32_t*>(w + L.plist), st);
-      const uint64_t waves = (ntok + 64ull * P->opt.tail_chunks - 1) / (64ull * P->opt.tail_chunks);
-      const uint32_t tgrid = uint32_t(std::min<uint64_t>((waves + 3) / 4, uint64_t(P->copy_grid)));
-      hipLaunchKernelGGL(k_tail, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);
+      if (ev) (void)hipEventRecord(ev[3], s);
+      if (!jump) {
+        uint32_t* pcnt = reinterpret_cast<uint32_t*>(w + L.pcnt);
+        hipLaunchKernelGGL(k_pcount, dim3(pgrid), dim3(kCopyThreads), 0, s, ca.pbits, n_words, pcnt);
+        hipLaunchKernelGGL(k_pscatter, dim3(pgrid), dim3(kCopyThreads), 0, s, ca.pbits, n_words, pcnt,
+                           reinterpret_cast<uint32_t*>(w + L.plist), st);
+      }
+      if (jump) {
+        // the last round marked the remainder (long tokens are marked here):
+        // list the map's busy words, settle the first entries, jump, write
+        ja.llist = ca.list_out;  // the last round's output sublists hold the long pending tokens
+        ja.lcnt = ca.cnt_out;
+        hipLaunchKernelGGL(k_jmarklong, dim3(grid), dim3(kCopyThreads), 0, s, ja);
+        const uint32_t lgrid = uint32_t((mwords + kJListWords - 1) / kJListWords);
+        hipLaunchKernelGGL(k_jlcount, dim3(lgrid), dim3(kCopyThreads), 0, s, ja);
+        hipLaunchKernelGGL(k_jlist, dim3(lgrid), dim3(kCopyThreads), 0, s, ja);
+        hipLaunchKernelGGL(k_jinit, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
+        const uint32_t passes = P->opt.jump_passes ? std::min<uint32_t>(P->jpass[wi], P->opt.jump_passes) : P->jpass[wi];
+        for (uint32_t p = 0; p < passes; ++p) {
+          ja.pass = p;
+          hipLaunchKernelGGL(k_jpass, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
+        }
+        hipLaunchKernelGGL(k_jgather, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
+        if (feedback) (void)hipMemcpyAsync(P->h_jused + wi, &st->jump_used, 4, hipMemcpyDeviceToHost, s);
+      } else {
+        const uint64_t waves = (ntok + 64ull * P->opt.tail_chunks - 1) / (64ull * P->opt.tail_chunks);
+        const uint32_t tgrid = uint32_t(std::min<uint64_t>((waves + 3) / 4, uint64_t(P->copy_grid)));
+        hipLaunchKernelGGL(k_tail, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);
+      }
     }
-    if (timed && last) (void)hipEventRecord(P->ev[3], s);
+    if (ev && !ntok) (void)hipEventRecord(ev[3], s);
+    if (ev) (void)hipEventRecord(ev[4], s);
   }
 }
 
@@ -1973,6 +2645,33 @@ int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_
   }
   uint8_t* w = static_cast<uint8_t*>(d_work);
   const bool timed = P->timing && P->events_ok;
+  // learned jump-pass counts: take the previous decode's report once it is in
+  if (P->jfeed_pending && hipEventQuery(P->jfed) == hipSuccess) {
+    P->jfeed_pending = false;
+    bool all = true;
+    for (size_t i = 0; i < P->wins.size(); ++i) {
+      const uint32_t used = P->h_jused[i];
+      if (used) P->jpass[i] = std::min(P->jpass[i], used + 1);
+      else all = false;
+    }
+    P->jsettled = all;
+    if (P->graph) (void)hipGraphExecDestroy(P->graph), P->graph = nullptr;  // pass counts changed
+  }
+  const bool feedback = P->learn && !P->jsettled && !P->jfeed_pending && P->opt.tail_mode == 0 && !P->opt.jump_passes &&
+                        copy_mode != AX_COPY_SERIAL && !P->wins.empty();
+  if (feedback) {
+    if (P->wins.size() > P->jused_cap) {
+      if (P->h_jused) (void)hipHostFree(P->h_jused), P->h_jused = nullptr;
+      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&P->h_jused), 4 * P->wins.size());
+      if (e != hipSuccess) return hip_fail(e, "pass report staging");
+      P->jused_cap = P->wins.size();
+    }
+    if (!P->jfed) {
+      hipError_t e = hipEventCreateWithFlags(&P->jfed, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "pass report event");
+    }
+    std::fill(P->h_jused, P->h_jused + P->wins.size(), 0u);
+  }
   if (P->opt.graph && !timed) {
     // the launch sequence of every window and round, captured once and replayed
     if (!P->graph || P->graph_work != d_work || P->graph_mode != copy_mode) {
@@ -1984,7 +2683,7 @@ int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_
       }
       hipError_t e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "graph capture");
-      enqueue(P, w, copy_mode, P->cap_stream, false);
+      enqueue(P, w, copy_mode, P->cap_stream, false, false);
       e = hipStreamEndCapture(P->cap_stream, &P->graph_def);
       if (e == hipSuccess) e = hipGraphInstantiate(&P->graph, P->graph_def, nullptr, nullptr, 0);
       if (e != hipSuccess) return hip_fail(e, "graph instantiate");
@@ -1995,9 +2694,19 @@ int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_
     if (e != hipSuccess) return hip_fail(e, "graph launch");
     return AX_OK;
   }
-  enqueue(P, w, copy_mode, s, timed);
+  if (timed) {
+    int rc = ensure_events(P);
+    if (rc) return rc;
+  }
+  enqueue(P, w, copy_mode, s, timed, feedback);
+  if (timed) P->timed_windows = P->wins.size();
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  if (feedback) {
+    e = hipEventRecord(P->jfed, s);
+    if (e != hipSuccess) return hip_fail(e, "pass report event");
+    P->jfeed_pending = true;
+  }
   return AX_OK;
 }
 
@@ -2112,9 +2821,9 @@ int aceapex_decoder_set_option(aceapex_decoder* d, int option, int64_t value) {
   return ax::plan_set_option(d->plan, option, value);
 }
 
-int aceapex_decoder_stage_ms(aceapex_decoder* d, float* ans, float* parse, float* copy) {
+int aceapex_decoder_stage_ms(aceapex_decoder* d, float* ans, float* parse, float* copy, float* remainder) {
   if (!d || !ans || !parse || !copy) return ax::fail(AX_E_ARG, "null argument");
-  return ax::plan_stage_ms(d->plan, ans, parse, copy);
+  return ax::plan_stage_ms(d->plan, ans, parse, copy, remainder);
 }
 
 int aceapex_decode_all(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, void* d_work, uint64_t work_len,
@@ -2188,9 +2897,9 @@ int aceapex_batch_set_timing(aceapex_batch* bt, int enable) {
   return ax::plan_set_timing(bt->plan, enable);
 }
 
-int aceapex_batch_stage_ms(aceapex_batch* bt, float* ans, float* parse, float* copy) {
+int aceapex_batch_stage_ms(aceapex_batch* bt, float* ans, float* parse, float* copy, float* remainder) {
   if (!bt || !ans || !parse || !copy) return ax::fail(AX_E_ARG, "null argument");
-  return ax::plan_stage_ms(bt->plan, ans, parse, copy);
+  return ax::plan_stage_ms(bt->plan, ans, parse, copy, remainder);
 }
 
 int aceapex_decode_batch(aceapex_batch* bt, void* d_work, uint64_t work_len, int copy_mode, void* stream) {

@@ -20,6 +20,8 @@ struct PlanOptions {
   int tail_chunks = 1;  // 64-token chunks per persistent-launch ticket
   int round0_tile = 1;  // round 0: a workgroup per block through an LDS tile (1) or a wave per 64 tokens (0)
   int graph = 0;        // replay the launch sequence from a captured hipGraph
+  int tail_mode = 0;    // deep remainder: pointer jumping (0) or the persistent chase (1)
+  int jump_passes = 0;  // at most this many jump passes per window (0: automatic)
 };
 
 // One archive to decode: all blocks (blocks empty) or the listed blocks
@@ -43,6 +45,9 @@ int plan_reset(Plan* p, const std::vector<JobSpec>& jobs, hipStream_t s);
 // Workspace of a one-window plan of decoder d with these maxima.
 uint64_t plan_workspace_for(const aceapex_decoder* d, uint64_t max_blocks, uint64_t max_tokens);
 void plan_copy_options(Plan* dst, const Plan* src);
+// Whether a plan learns its jump-pass counts from its own decodes (on by
+// default; off for plans rebuilt for every call).
+void plan_set_learn(Plan* p, bool learn);
 // Entropy + parse only, every window; the match tokens (src; dst | (len-1)
 // << 48) are copied to host arrays in archive order.  Synchronous.
 int plan_parse_tokens(Plan* p, void* d_work, uint64_t work_len, hipStream_t s, uint64_t* src, uint64_t* dstlen);
@@ -54,7 +59,7 @@ int plan_set_out(Plan* p, size_t job, uint8_t* out);
 int plan_set_option(Plan* p, int option, int64_t value);
 int plan_get_option(const Plan* p, int option, int64_t* value);
 int plan_set_timing(Plan* p, int enable);
-int plan_stage_ms(Plan* p, float* ans, float* parse, float* copy);
+int plan_stage_ms(Plan* p, float* ans, float* parse, float* copy, float* remainder);
 int plan_run(Plan* p, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s);
 int workspace_status(void* d_work, hipStream_t s, int32_t* dev_err, uint64_t* bad_block);
 

@@ -315,6 +315,7 @@ int aceapex_decode_ranges(aceapex_range_plan* rp, uint32_t n, const uint64_t* of
   if (!bl.empty()) {
     if (!rp->plan) {
       rc = ax::plan_create({ax::JobSpec{d, d_full, std::move(bl)}}, &rp->plan);
+      if (!rc) ax::plan_set_learn(rp->plan, false);
     } else {
       rc = ax::plan_reset(rp->plan, {ax::JobSpec{d, d_full, std::move(bl)}}, s);
     }

@@ -219,13 +219,17 @@ def test_deep_cross_block_chain():
 # -------------------------------------------------------------- behaviour --
 
 @pytest.mark.parametrize("opts", [
-    {ax.OPT_BULK_ROUNDS: 1}, {ax.OPT_BULK_ROUNDS: 2, ax.OPT_TAIL_CHUNKS: 4},
-    {ax.OPT_BULK_ROUNDS: 8, ax.OPT_FILL_ROUNDS: 0, ax.OPT_FILL_TAIL: 1},
-    {ax.OPT_BULK_ROUNDS: 3, ax.OPT_FILL_TAIL: 1, ax.OPT_TAIL_CHUNKS: 16},
-    {ax.OPT_ROUND0_TILE: 0}, {ax.OPT_ROUND0_TILE: 0, ax.OPT_FILL_ROUNDS: 1, ax.OPT_BULK_ROUNDS: 1}])
+    {ax.OPT_BULK_ROUNDS: 1}, {ax.OPT_BULK_ROUNDS: 2, ax.OPT_TAIL_CHUNKS: 4, ax.OPT_TAIL_MODE: 1},
+    {ax.OPT_BULK_ROUNDS: 8, ax.OPT_FILL_ROUNDS: 0, ax.OPT_FILL_TAIL: 1, ax.OPT_TAIL_MODE: 1},
+    {ax.OPT_BULK_ROUNDS: 3, ax.OPT_FILL_TAIL: 1, ax.OPT_TAIL_CHUNKS: 16, ax.OPT_TAIL_MODE: 1},
+    {ax.OPT_ROUND0_TILE: 0}, {ax.OPT_ROUND0_TILE: 0, ax.OPT_FILL_ROUNDS: 1, ax.OPT_BULK_ROUNDS: 1},
+    {ax.OPT_TAIL_MODE: 1}, {ax.OPT_BULK_ROUNDS: 1, ax.OPT_JUMP_PASSES: 1},
+    {ax.OPT_BULK_ROUNDS: 2, ax.OPT_JUMP_PASSES: 3}, {ax.OPT_BULK_ROUNDS: 6}])
 def test_schedule_options_change_no_byte(opts):
-    """Every schedule knob (rounds, fill modes, tickets per chunk run, round-0 schedule)
-    decodes a deep text archive and a DNA archive to the oracle's bytes."""
+    """Every schedule knob (rounds, fill modes, tickets per chunk run, round-0
+    schedule, deep-remainder mode, jump pass limit: with one or three passes
+    the gather follows the remaining chains itself) decodes a deep text
+    archive and a DNA archive to the oracle's bytes."""
     for name, x in (("text", synth.text(3 << 20, 46)), ("dna", synth.dna(3 << 20, 47))):
         arc, _ = oracle.encode(x)
         dec = ax.Decoder(arc, torch.from_numpy(arc).cuda())
