@@ -72,8 +72,8 @@ def parse_args():
     ap.add_argument("--requests", type=int, default=10000, help="requests per serving trace point")
     ap.add_argument("--sizes", default="16k,mixed", help="serving request sizes: 16k and/or mixed (16 KiB-1 MiB)")
     ap.add_argument("--slots", type=int, default=3, help="serving slots (concurrent batches)")
-    ap.add_argument("--max-blocks", type=int, default=32768, help="serving admission limit: closure blocks per batch")
-    ap.add_argument("--max-tokens", type=int, default=1 << 23, help="serving admission limit: matches per batch")
+    ap.add_argument("--max-blocks", type=int, default=8192, help="serving admission limit: closure blocks per batch")
+    ap.add_argument("--max-tokens", type=int, default=1 << 21, help="serving admission limit: matches per batch")
     ap.add_argument("--bulk-rounds", type=int, default=0, help="level-synchronous copy rounds (0 = library default)")
     ap.add_argument("--tail-chunks", type=int, default=0, help="chunks per persistent-launch ticket (0 = default)")
     ap.add_argument("--fill", default="", help="fill modes 'R,T' for rounds and tail (0 lane/wave, 1 segmented)")
@@ -154,36 +154,37 @@ def _pcts(ns):
     return round(float(np.percentile(ns, 50)) / 1e3, 1), round(float(np.percentile(ns, 99)) / 1e3, 1)
 
 
-def read_latency(ax, dec, x, full, count, size, seed, max_blocks, max_tokens):
+def read_latency(ax, dec, x, count, size, seed):
     """Closed loop: `count` reads of `size` bytes at trace-generated offsets
-    (80% Zipf-local, 20% uniform), each issued alone and waited for.  Latency
-    runs from the host call (closure, plan upload, kernels) to the device
-    event after the copy-out; every read is checked against the input."""
+    (80% Zipf-local, 20% uniform), each issued alone through
+    aceapex_decode_range and waited for, with a workspace of the largest
+    aceapex_range_workspace among them.  Latency runs from the host call
+    (closure, plan upload, kernels) to the device event after the copy-out;
+    every read is checked against the input."""
     import torch
 
     import synth
 
-    dev = full.device
+    dev = dec.device
     _, offs, lens = synth.trace(count, seed, x.size, 16384, 1000.0, size, size)
-    plan = ax.RangePlan(dec, max_blocks, max_tokens)
-    work = torch.empty(max(256, plan.workspace_bytes), dtype=torch.uint8, device=dev)
+    need = max(dec.range_workspace(int(o), size) for o in offs)
+    work = torch.empty(max(256, need), dtype=torch.uint8, device=dev)
     outs = torch.empty((count, size), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
-    lat, blocks = [], []
+    lat = []
     for i in range(count):
         torch.cuda.synchronize()
         t = time.perf_counter_ns()
-        plan.decode([int(offs[i])], [size], [outs[i]], full, work, stream=stream)
+        dec.decode_range(int(offs[i]), size, outs[i], work, stream=stream)
         end = torch.cuda.Event()
         end.record(stream)
         end.synchronize()
         lat.append(time.perf_counter_ns() - t)
-        blocks.append(plan.last()[0])
     got = outs.cpu().numpy()
     bad = sum(not np.array_equal(got[i], x[int(offs[i]): int(offs[i]) + size]) for i in range(count))
     p50, p99 = _pcts(lat)
     return {"p50_us": p50, "p99_us": p99, "reads": count, "bytes": size, "mismatches": int(bad),
-            "closure_blocks_mean": round(float(np.mean(blocks)), 1), "mode": "closed loop, one read at a time"}
+            "workspace_bytes": int(need), "mode": "closed loop, one read at a time"}
 
 
 # ------------------------------------------------- served workload (config 5)
@@ -221,8 +222,7 @@ def run_serve(args, log):
     t0 = time.time()
     srv = Server(arc, d_arc, slots=args.slots, max_blocks=args.max_blocks, max_tokens=args.max_tokens)
     log(f"server ready in {time.time() - t0:.1f}s (token index built on the device)")
-    unloaded = read_latency(ax, srv.dec, x, srv.slots[0]["full"], args.reads, 16384, 54, args.max_blocks,
-                            args.max_tokens)
+    unloaded = read_latency(ax, srv.dec, x, args.reads, 16384, 54)
     log(f"unloaded 16 KiB reads: p50 {unloaded['p50_us']} us, p99 {unloaded['p99_us']} us")
 
     rates = [float(r) for r in args.rates.split(",") if r]
@@ -270,6 +270,7 @@ def run_serve(args, log):
         "config": {"workload": f"synthetic DNA {n} B held compressed ({arc.size} B), Poisson range reads",
                    "n_bytes": n, "archive_bytes": int(arc.size), "blocks": int(st.n_blocks),
                    "matches": int(st.n_matches), "slots": args.slots, "max_blocks": args.max_blocks,
+                   "serving_workspace_bytes": int(srv.workspace_bytes),
                    "max_tokens": args.max_tokens, "requests_per_point": count},
         "unloaded_16k": unloaded, "points": points,
     }
@@ -591,8 +592,8 @@ def main():
     }
     if args.reads:
         t0 = time.time()
-        dec.build_index(out, work=work)
-        res["read_16k"] = read_latency(ax, dec, x, out, args.reads, 16384, 54, 32768, 1 << 23)
+        dec.build_index(work=work)
+        res["read_16k"] = read_latency(ax, dec, x, args.reads, 16384, 54)
         log(f"16 KiB reads: {res['read_16k']} ({time.time() - t0:.1f}s)")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(arc, n, x)

@@ -193,7 +193,9 @@ enum { AX_OPT_ROUND0_TILE = 6 };
  *     log2(chain length) passes replaces that name by the one it names
  *     (default); 1 = one persistent launch that copies each token once the
  *     tokens writing its sources are done (one dependency hop at a time; the
- *     serial copy mode always finishes this way). */
+ *     serial copy mode always finishes this way).  Range decodes choose by
+ *     their closure: the persistent launch below 65536 matches, jumping
+ *     above. */
 enum { AX_OPT_TAIL_MODE = 7 };
 /*   AX_OPT_JUMP_PASSES  0 = automatic: the first decode runs enough passes
  *     for any chain of the window (log2 of its token count) and later ones the
@@ -240,13 +242,11 @@ int aceapex_decode_batch(aceapex_batch* batch, void* d_work, uint64_t work_len, 
 /* -------------------------------------------------------- random access --- */
 
 /* Build the decoder's token index (every match: src, dst, len) on the host,
- * by a device entropy + parse pass over the archive (random-access section:
- * the index is what makes a range's source closure computable without
- * decoding the archive).  d_full: a device buffer of info.n_bytes (receives
- * literal bytes as a side effect); d_work: the decode_all workspace.
- * Synchronous; host memory 16 bytes per match. */
-int aceapex_decoder_build_index(aceapex_decoder* dec, uint8_t* d_full, void* d_work, uint64_t work_len,
-                                void* stream);
+ * by a device entropy + parse pass over the archive that writes no output
+ * bytes (random-access section: the index is what makes a range's source
+ * closure computable without decoding the archive).  d_work: the
+ * decode_all workspace.  Synchronous; host memory 16 bytes per match. */
+int aceapex_decoder_build_index(aceapex_decoder* dec, void* d_work, uint64_t work_len, void* stream);
 
 /* Byte-precise source closure of n ranges: the ascending union of the blocks
  * holding any byte the ranges need (their own bytes and, transitively, the
@@ -258,9 +258,31 @@ int aceapex_closure_blocks(aceapex_decoder* dec, uint32_t n, const uint64_t* h_o
                            uint64_t* h_blocks, uint64_t cap, uint64_t* n_blocks, uint64_t* n_tokens,
                            uint32_t threads);
 
+/* Device workspace (bytes, 256-byte aligned start) that aceapex_decode_range
+ * needs for the range [off, off + len): the decode workspace of its source
+ * closure, a compact scratch of (closure blocks + 1) * block_size bytes and
+ * a slot table of 4 bytes per archive block — sized by the closure, not by
+ * the archive (Introduction: decompressing everything leaves nowhere to put
+ * it).  Needs the token index.  AX_E_CAPACITY when the closure exceeds one
+ * window (131072 blocks or 2^26 matches). */
+int aceapex_range_workspace(const aceapex_decoder* dec, uint64_t off, uint64_t len, uint64_t* bytes);
+
+/* Decode the byte range [off, off + len) into d_out[0..len) (device,
+ * out_cap >= len): the range's source closure is decoded into the compact
+ * scratch inside d_work (at least aceapex_range_workspace bytes) and the
+ * range copied out (random-access section: one tile or a range of blocks
+ * from a resident archive).  The closure is computed on the host first;
+ * the decode is asynchronous on `stream`.  Errors before any launch:
+ * AX_E_RANGE (outside the archive), AX_E_CAPACITY (d_out or d_work too
+ * small), AX_E_ARG. */
+int aceapex_decode_range(aceapex_decoder* dec, uint64_t off, uint64_t len, uint8_t* d_out, uint64_t out_cap,
+                         void* d_work, uint64_t work_len, void* stream);
+
 /* A reusable range-decode plan with capacity limits (blocks and matches of
- * one call's closure, at most 131072 blocks and 2^26 matches); its workspace
- * size depends only on the limits. */
+ * one call's union closure, at most 131072 blocks and 2^26 matches): the
+ * batched form for serving.  Its workspace size depends only on the limits:
+ * the decode workspace for them, a compact scratch of (max_blocks + 1)
+ * blocks and the slot table. */
 typedef struct aceapex_range_plan aceapex_range_plan;
 int aceapex_range_plan_create(aceapex_decoder* dec, uint64_t max_blocks, uint64_t max_tokens,
                               aceapex_range_plan** out);
@@ -270,20 +292,17 @@ int aceapex_range_plan_workspace(const aceapex_range_plan* rp, uint64_t* bytes);
 int aceapex_range_plan_last(const aceapex_range_plan* rp, uint64_t* blocks, uint64_t* tokens);
 
 /* Decode n byte ranges [h_offs[i], h_offs[i] + h_lens[i]) of the archive:
- * their union closure is decoded into d_full (a device buffer of
- * info.n_bytes, at absolute positions; bytes outside the closure are left
- * as they were) and range i is then copied to d_outs[i] (a host array of
- * device pointers, h_lens[i] bytes each).  The closure is computed on the
+ * their union closure is decoded into the compact scratch inside d_work and
+ * range i is copied to h_d_outs[i] (a host array of device pointers, each
+ * with h_out_caps[i] >= h_lens[i] bytes).  The closure is computed on the
  * host before anything is enqueued; the decode and the copies are
- * asynchronous on `stream`.  AX_E_CAPACITY when the closure exceeds the
- * plan's limits, AX_E_RANGE for a range outside the archive.  Calls sharing
- * d_full or d_work must be ordered (same stream). */
+ * asynchronous on `stream`.  Errors before any launch: AX_E_CAPACITY when
+ * the closure exceeds the plan's limits or an output or the workspace is too
+ * small, AX_E_RANGE for a range outside the archive.  Calls sharing d_work
+ * must be ordered (same stream). */
 int aceapex_decode_ranges(aceapex_range_plan* rp, uint32_t n, const uint64_t* h_offs, const uint64_t* h_lens,
-                          uint8_t* const* h_d_outs, uint8_t* d_full, void* d_work, uint64_t work_len, int copy_mode,
-                          void* stream);
-/* One range (aceapex_decode_ranges with n = 1, periodic copy). */
-int aceapex_decode_range(aceapex_range_plan* rp, uint64_t off, uint64_t len, uint8_t* d_out, uint8_t* d_full,
-                         void* d_work, uint64_t work_len, void* stream);
+                          uint8_t* const* h_d_outs, const uint64_t* h_out_caps, void* d_work, uint64_t work_len,
+                          int copy_mode, void* stream);
 
 #ifdef __cplusplus
 }

@@ -27,6 +27,7 @@ EXPORTS = [
     "aceapex_batch_set_option", "aceapex_batch_set_timing", "aceapex_batch_stage_ms", "aceapex_decode_batch",
     "aceapex_decoder_build_index", "aceapex_closure_blocks", "aceapex_range_plan_create", "aceapex_range_plan_destroy",
     "aceapex_range_plan_workspace", "aceapex_range_plan_last", "aceapex_decode_ranges", "aceapex_decode_range",
+    "aceapex_range_workspace",
 ]
 OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH, OPT_ROUND0_TILE = 1, 2, 3, 4, 5, 6
 OPT_TAIL_MODE, OPT_JUMP_PASSES = 7, 8
@@ -106,15 +107,16 @@ def _load():
     L.aceapex_batch_stage_ms.argtypes = [vp] + [P(ctypes.c_float)] * 4
     L.aceapex_decode_batch.argtypes = [vp, vp, u64, ctypes.c_int, vp]
     u64p = P(u64)
-    L.aceapex_decoder_build_index.argtypes = [vp, vp, vp, u64, vp]
+    L.aceapex_decoder_build_index.argtypes = [vp, vp, u64, vp]
     L.aceapex_closure_blocks.argtypes = [vp, ctypes.c_uint32, u64p, u64p, u64p, u64, u64p, u64p, ctypes.c_uint32]
     L.aceapex_range_plan_create.argtypes = [vp, u64, u64, P(vp)]
     L.aceapex_range_plan_destroy.argtypes = [vp]
     L.aceapex_range_plan_destroy.restype = None
     L.aceapex_range_plan_workspace.argtypes = [vp, u64p]
     L.aceapex_range_plan_last.argtypes = [vp, u64p, u64p]
-    L.aceapex_decode_ranges.argtypes = [vp, ctypes.c_uint32, u64p, u64p, P(vp), vp, vp, u64, ctypes.c_int, vp]
-    L.aceapex_decode_range.argtypes = [vp, u64, u64, vp, vp, vp, u64, vp]
+    L.aceapex_decode_ranges.argtypes = [vp, ctypes.c_uint32, u64p, u64p, P(vp), u64p, vp, u64, ctypes.c_int, vp]
+    L.aceapex_decode_range.argtypes = [vp, u64, u64, vp, u64, vp, u64, vp]
+    L.aceapex_range_workspace.argtypes = [vp, u64, u64, u64p]
     _lib = L
     return L
 
@@ -243,11 +245,26 @@ class Decoder:
                                               ctypes.byref(err), ctypes.byref(bad)), "decoder_status")
         return err.value, bad.value
 
-    def build_index(self, full, stream=None, work=None):
+    def build_index(self, stream=None, work=None):
         """Token index for range closures (device parse pass; synchronous)."""
         w = self.workspace() if work is None else work
-        _check(_load().aceapex_decoder_build_index(self._h, ctypes.c_void_p(full.data_ptr()), ctypes.c_void_p(w.data_ptr()),
-                                                   w.numel(), _stream_ptr(stream)), "build_index")
+        _check(_load().aceapex_decoder_build_index(self._h, ctypes.c_void_p(w.data_ptr()), w.numel(),
+                                                   _stream_ptr(stream)), "build_index")
+
+    def range_workspace(self, off, length):
+        """Device workspace bytes aceapex_decode_range needs for [off, off+length)."""
+        b = ctypes.c_uint64()
+        _check(_load().aceapex_range_workspace(self._h, int(off), int(length), ctypes.byref(b)), "range_workspace")
+        return b.value
+
+    def decode_range(self, off, length, out, work, stream=None):
+        """Enqueue the decode of one byte range into `out` (a CUDA uint8
+        tensor of at least `length` bytes); `work` holds at least
+        range_workspace(off, length) bytes."""
+        _check(_load().aceapex_decode_range(self._h, int(off), int(length), ctypes.c_void_p(out.data_ptr()),
+                                            out.numel(), ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                            _stream_ptr(stream)), "decode_range")
+        return out
 
     def closure_blocks(self, offs, lens, threads=0, want_blocks=True):
         """Union source closure of ranges: (ascending block array, match count)."""
@@ -361,15 +378,17 @@ class RangePlan:
         _check(_load().aceapex_range_plan_last(self._h, ctypes.byref(b), ctypes.byref(t)), "range_plan_last")
         return b.value, t.value
 
-    def decode(self, offs, lens, outs, full, work, copy_mode=COPY_PERIODIC, stream=None):
-        """Enqueue the decode of ranges; outs: CUDA uint8 tensors (len each).
-        Raises AceapexError(AX_E_CAPACITY) when the closure exceeds the limits."""
+    def decode(self, offs, lens, outs, work, copy_mode=COPY_PERIODIC, stream=None):
+        """Enqueue the decode of ranges; outs: CUDA uint8 tensors (at least
+        len bytes each).  Raises AceapexError(AX_E_CAPACITY) when the closure
+        exceeds the limits or an output is too small."""
         n = len(offs)
         o = np.ascontiguousarray(offs, dtype=np.uint64)
         ln = np.ascontiguousarray(lens, dtype=np.uint64)
+        caps = np.ascontiguousarray([t.numel() for t in outs], dtype=np.uint64)
         ptrs = (ctypes.c_void_p * max(1, n))(*[t.data_ptr() for t in outs])
         u64p = ctypes.POINTER(ctypes.c_uint64)
         rc = _load().aceapex_decode_ranges(self._h, n, o.ctypes.data_as(u64p), ln.ctypes.data_as(u64p), ptrs,
-                                           ctypes.c_void_p(full.data_ptr()), ctypes.c_void_p(work.data_ptr()),
+                                           caps.ctypes.data_as(u64p), ctypes.c_void_p(work.data_ptr()),
                                            work.numel(), int(copy_mode), _stream_ptr(stream))
         _check(rc, "decode_ranges")

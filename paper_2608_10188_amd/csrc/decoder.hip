@@ -86,10 +86,15 @@ static_assert(sizeof(DevStatus) == 256, "status block is 256 bytes");
 // the source closure of a range): where it is, and where its bytes go.
 struct JobDev {
   const uint8_t* arc;   // device archive
-  uint8_t* out;         // decoded bytes at the archive's absolute positions
+  uint8_t* out;         // decoded bytes: at the archive's absolute positions, or by slot (below)
   uint64_t payload_at;  // header + index bytes
   uint64_t n_bytes, nb;
   uint32_t B, mm;
+  // a range decode's compact scratch: block b's bytes at out + slot[b] * B;
+  // a slot of `junk` or more means the junk block (blocks the plan does not
+  // decode; only bytes nobody needs are read from it).  null: absolute.
+  const uint32_t* slot;
+  uint32_t junk;
 };
 
 // One block of a window.  A window holds the blocks of its jobs job by job
@@ -101,6 +106,37 @@ struct WinBlock {
   uint32_t tok;     // window index of the block's first token
   uint32_t first;   // window index of this job's first block in the window
   uint32_t count;   // blocks of this job in the window
+};
+
+// Where the bytes of archive position p of a job's output live.  OutDirect:
+// the output holds the archive at its absolute positions (whole-archive and
+// batch decodes).  OutMapped: a range decode's compact scratch, the bytes of
+// block b at slot[b] * B (the slot table is set for the blocks the plan
+// decodes; any other block maps to the junk block, whatever its entry holds,
+// so a stale entry can never send an access outside the scratch).  Copy
+// kernels are instantiated for each; the whole-archive path compiles to the
+// plain pointer arithmetic.
+typedef AX_GLOBAL uint8_t* gbytes;
+struct OutDirect {
+  gbytes base;
+  __device__ explicit OutDirect(const JobDev& j) : base(gp(j.out)) {}
+  __device__ OutDirect with_base(gbytes b) const { OutDirect o = *this; o.base = b; return o; }
+  __device__ gbytes at(uint64_t p) const { return base + p; }
+  __device__ bool contiguous(uint64_t, uint32_t) const { return true; }  // n bytes from p in one piece
+};
+struct OutMapped {
+  gbytes base;
+  const AX_GLOBAL uint32_t* slot;
+  uint32_t lb, junk;
+  __device__ explicit OutMapped(const JobDev& j)
+      : base(gp(j.out)), slot(gp(j.slot)), lb(uint32_t(__builtin_ctz(j.B))), junk(j.junk) {}
+  __device__ OutMapped with_base(gbytes b) const { OutMapped o = *this; o.base = b; return o; }
+  __device__ gbytes at(uint64_t p) const {
+    uint32_t x = slot[p >> lb];
+    if (x >= junk) x = junk;
+    return base + (uint64_t(x) << lb) + (p & ((1u << lb) - 1u));
+  }
+  __device__ bool contiguous(uint64_t p, uint32_t n) const { return (p & ((1u << lb) - 1u)) + n <= (1u << lb); }
 };
 
 __device__ inline uint32_t job_off_cap(const JobDev& j) { return (10u * (j.B / j.mm + 1) + 15u) & ~15u; }
@@ -372,6 +408,7 @@ struct ParseArgs {
   uint32_t* tblk;            // per token: its window block
   uint8_t* done;             // per token: kPending until the match layer copies it
   DevStatus* st;
+  int write_out;             // 0: tokens only (the token-index build), no output bytes
 };
 
 // History maps.  A command acts on the four-entry distance history as a map
@@ -584,6 +621,7 @@ __device__ bool leb_values(Src src, uint32_t n, uint32_t* cursor, uint32_t count
 }
 
 // Six waves per SIMD (at most 80 VGPRs), as many as the LDS allows.
+template <class O>
 __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
   __shared__ ParseShared sh;
   const uint32_t item = blockIdx.x, t = threadIdx.x;
@@ -779,8 +817,9 @@ __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
     if (t == 0) report(a.st, AX_E_CORRUPT, b);
     return;
   }
+  if (!a.write_out) return;
   // write the tile with 16-byte stores (match bytes are filled by the match layer)
-  AX_GLOBAL uint8_t* o = gp(J.out + bs);
+  AX_GLOBAL uint8_t* o = O(J).at(bs);  // the block's bytes are contiguous
   const uint32_t full = blen & ~15u;
   for (uint32_t k = 16 * t; k < full; k += 16 * kParseThreads)
     *reinterpret_cast<AX_GLOBAL u32x4*>(o + k) = *reinterpret_cast<const u32x4*>(sh.tile + k);
@@ -863,9 +902,9 @@ __device__ inline void find_cover(const CopyArgs& a, const WinBlock& wb, uint32_
   while (p + cnt < end_tok && (a.tok[2 * uint64_t(p + cnt) + 1] & ((1ull << 48) - 1)) < s1) ++cnt;
 }
 
-// The output base of token t's archive.
-typedef AX_GLOBAL uint8_t* gbytes;
-__device__ inline gbytes token_out(const CopyArgs& a, uint32_t t) { return gp(a.jobs[a.wbl[a.tblk[t]].job].out); }
+// The output of token t's archive.
+template <class O>
+__device__ inline O token_out(const CopyArgs& a, uint32_t t) { return O(a.jobs[a.wbl[a.tblk[t]].job]); }
 
 template <bool COH>
 __device__ inline uint8_t ldb(const AX_GLOBAL uint8_t* p) {
@@ -880,10 +919,10 @@ __device__ inline void stb(gbytes p, uint8_t v) {
 
 // The serial ablation: one lane, byte after byte, reading the bytes it may
 // itself have just written (a self-overlapping match is a dependency chain).
-template <bool COH>
-__device__ inline void fill_serial(gbytes out, uint64_t dst, uint64_t src, uint32_t len) {
+template <bool COH, class O>
+__device__ inline void fill_serial(const O& out, uint64_t dst, uint64_t src, uint32_t len) {
   for (uint32_t k = 0; k < len; ++k) {
-    stb<COH>(out + dst + k, ldb<COH>(out + src + k));
+    stb<COH>(out.at(dst + k), ldb<COH>(out.at(src + k)));
     __builtin_amdgcn_s_waitcnt(0x0F70);  // the next load may read this byte
   }
 }
@@ -891,8 +930,8 @@ __device__ inline void fill_serial(gbytes out, uint64_t dst, uint64_t src, uint3
 // One lane fills a token as a periodic fill: sixteen source loads in flight,
 // then sixteen stores.  The source index runs over the period dist (for
 // dist >= len it never wraps and the fill is a plain copy).
-template <bool COH>
-__device__ inline void fill_lane(gbytes out, uint64_t dst, uint64_t src, uint32_t len) {
+template <bool COH, class O>
+__device__ inline void fill_lane(const O& out, uint64_t dst, uint64_t src, uint32_t len) {
   const uint64_t dist = dst - src;
   uint64_t j = 0;
   for (uint32_t k0 = 0; k0 < len; k0 += 16) {
@@ -904,16 +943,16 @@ __device__ inline void fill_lane(gbytes out, uint64_t dst, uint64_t src, uint32_
     }
     uint8_t v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = (k0 + q < len) ? ldb<COH>(out + src + idx[q]) : uint8_t(0);
+    for (int q = 0; q < 16; ++q) v[q] = (k0 + q < len) ? ldb<COH>(out.at(src + idx[q])) : uint8_t(0);
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-      if (k0 + q < len) stb<COH>(out + dst + k0 + q, v[q]);
+      if (k0 + q < len) stb<COH>(out.at(dst + k0 + q), v[q]);
   }
 }
 
 // The whole wave fills one long token: eight bytes per lane in flight.
-template <bool COH>
-__device__ inline void fill_wave(gbytes out, uint64_t dst, uint64_t src, uint32_t len, uint32_t lane) {
+template <bool COH, class O>
+__device__ inline void fill_wave(const O& out, uint64_t dst, uint64_t src, uint32_t len, uint32_t lane) {
   const uint64_t dist = dst - src;
   const uint64_t step = dist > 64 ? 64 : 64 % uint32_t(dist);  // no 64-bit division
   uint64_t j = dist > lane ? lane : lane % uint32_t(dist);
@@ -927,10 +966,10 @@ __device__ inline void fill_wave(gbytes out, uint64_t dst, uint64_t src, uint32_
     }
     uint8_t v[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = (k0 + 64 * q < len) ? ldb<COH>(out + src + idx[q]) : uint8_t(0);
+    for (int q = 0; q < 8; ++q) v[q] = (k0 + 64 * q < len) ? ldb<COH>(out.at(src + idx[q])) : uint8_t(0);
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      if (k0 + 64 * q < len) stb<COH>(out + dst + k0 + 64 * q, v[q]);
+      if (k0 + 64 * q < len) stb<COH>(out.at(dst + k0 + 64 * q), v[q]);
   }
 }
 
@@ -954,8 +993,8 @@ enum { kFillLaneWave = 0, kFillSegmented = 1 };
 // pass issues 64 * kFillBytes independent source loads before its stores,
 // whatever the mix of short and long tokens.  Byte k of a token comes from
 // src + (k mod dist) (dist >= len: a plain copy).
-template <bool COH>
-__device__ inline void fill_ready(gbytes out, bool ready, uint64_t dst, uint64_t src, uint32_t len, int serial,
+template <bool COH, class O>
+__device__ inline void fill_ready(const O& out, bool ready, uint64_t dst, uint64_t src, uint32_t len, int serial,
                                   int fill_mode, FillStage& fs) {
   const uint32_t lane = lane_id();
   if (serial) {
@@ -969,7 +1008,8 @@ __device__ inline void fill_ready(gbytes out, bool ready, uint64_t dst, uint64_t
     while (lm) {
       const int l = __builtin_ctzll(lm);
       lm &= lm - 1;
-      const gbytes o = reinterpret_cast<gbytes>(__shfl((unsigned long long)reinterpret_cast<uintptr_t>(out), l, 64));
+      const O o = out.with_base(
+          reinterpret_cast<gbytes>(__shfl((unsigned long long)reinterpret_cast<uintptr_t>(out.base), l, 64)));
       fill_wave<COH>(o, __shfl((unsigned long long)dst, l, 64), __shfl((unsigned long long)src, l, 64),
                      __shfl(len, l, 64), lane);
     }
@@ -982,7 +1022,7 @@ __device__ inline void fill_ready(gbytes out, bool ready, uint64_t dst, uint64_t
   fs.len[lane] = mine;
   fs.dst[lane] = dst;
   fs.src[lane] = src;
-  fs.out[lane] = out;
+  fs.out[lane] = out.base;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   for (uint32_t base = 0; base < total; base += 64 * kFillBytes) {
@@ -997,7 +1037,7 @@ __device__ inline void fill_ready(gbytes out, bool ready, uint64_t dst, uint64_t
         if (fs.end[l + step - 1] <= f0) l += step;
       uint32_t e = fs.end[l], start = e - fs.len[l];
       uint64_t d = fs.dst[l], sr = fs.src[l], dist = d - sr;
-      gbytes o = fs.out[l];
+      O o = out.with_base(fs.out[l]);
       uint64_t k = f0 - start;  // < 2^16: a token lies inside one block
       uint64_t j = dist > k ? k : uint64_t(uint32_t(k) % uint32_t(dist));
 #pragma unroll
@@ -1008,11 +1048,11 @@ __device__ inline void fill_ready(gbytes out, bool ready, uint64_t dst, uint64_t
           e = fs.end[l];
           start = e - fs.len[l];
           d = fs.dst[l], sr = fs.src[l], dist = d - sr;
-          o = fs.out[l];
+          o = out.with_base(fs.out[l]);
           k = 0, j = 0;
         }
-        at[q] = reinterpret_cast<uint64_t>(o + sr + j);
-        to[q] = f < total ? reinterpret_cast<uint64_t>(o + d + k) : ~0ull;
+        at[q] = reinterpret_cast<uint64_t>(o.at(sr + j));
+        to[q] = f < total ? reinterpret_cast<uint64_t>(o.at(d + k)) : ~0ull;
         ++k;
         if (++j == dist) j = 0;
       }
@@ -1080,6 +1120,7 @@ __device__ inline bool window_block(const WinBlock* wbl, uint32_t S, const WinBl
 // when not null, every token lies in window block `row_item` and its bits go
 // to that block's LDS row (32-bit words); else to the leftover map with
 // global atomics.
+template <class O>
 __device__ void mark_wave(const CopyArgs& a, bool pend, uint32_t t, MarkStage& ms, uint32_t* row,
                           uint32_t row_item) {
   const uint32_t lane = lane_id();
@@ -1150,7 +1191,7 @@ __device__ void mark_wave(const CopyArgs& a, bool pend, uint32_t t, MarkStage& m
         cb = sb;
         cin = window_block(a.wbl, a.S, wb, sb, cbase);
       }
-      const uint32_t v = cin ? cbase + uint32_t(sp & (jd.B - 1)) : kJRes | gp(jd.out)[sp];
+      const uint32_t v = cin ? cbase + uint32_t(sp & (jd.B - 1)) : kJRes | *O(jd).at(sp);
       const uint32_t d = item * a.S + uint32_t(dst - bs) + k;  // this byte's window position
       J[d] = v;
       if ((d >> 5) != mw) {
@@ -1188,6 +1229,7 @@ __device__ void mark_wave(const CopyArgs& a, bool pend, uint32_t t, MarkStage& m
 // read nor written.  Tokens of at least kSplitToken bytes go to k_long.
 // Leftovers go to sublist (t / 64) mod kSub, so a sublist holds at most
 // ceil(T / 64 / kSub) * 64 tokens.
+template <class O>
 __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t tile[kMaxB];
   __shared__ uint32_t dirty[kMaxB / 16 / 32];  // chunks of the tile that receive match bytes
@@ -1198,9 +1240,10 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
   const WinBlock wb = a.wbl[item];
   const JobDev& J = a.jobs[wb.job];
-  const gbytes out = gp(J.out);
+  const O out(J);
   const uint32_t B = J.B;
   const uint64_t bs = wb.b * B;
+  const gbytes ob = out.at(bs);  // this block's bytes (contiguous)
   const uint32_t blen = uint32_t(min<uint64_t>(B, J.n_bytes - bs));
   const uint32_t nchunk = (blen + 15) / 16;
   const uint32_t t1 = item + 1 < a.n_items ? a.wbl[item + 1].tok : a.n_tok;
@@ -1264,9 +1307,9 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   for (uint32_t k = threadIdx.x; k < nchunk; k += kCopyThreads) {
     if (!((dirty[k >> 5] >> (k & 31)) & 1)) continue;
     if (k < full) {
-      *reinterpret_cast<u32x4*>(tile + 16 * k) = *reinterpret_cast<const AX_GLOBAL u32x4*>(out + bs + 16 * k);
+      *reinterpret_cast<u32x4*>(tile + 16 * k) = *reinterpret_cast<const AX_GLOBAL u32x4*>(ob + 16 * k);
     } else {
-      for (uint32_t i = 16 * k; i < blen; ++i) tile[i] = out[bs + i];
+      for (uint32_t i = 16 * k; i < blen; ++i) tile[i] = ob[i];
     }
   }
   __syncthreads();
@@ -1284,14 +1327,14 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
     if (mine && a.serial) {  // the ablation: byte after byte, in-block sources read back from the tile
       for (uint32_t k = 0; k < len; ++k) {
         const uint64_t p = src + k;
-        tile[drel + k] = p < bs ? out[p] : tile[p - bs];
+        tile[drel + k] = p < bs ? *out.at(p) : tile[p - bs];
       }
     } else if (mine) {
       const uint64_t dist = dst - src;
       uint64_t j = 0;
       for (uint32_t k0 = 0; k0 < len; k0 += 16) {
-        if (src + k0 + 16 <= dst) {  // 16 source bytes before the destination: one unaligned load
-          const u32x4 v = *reinterpret_cast<const AX_GLOBAL u32x4_u*>(out + src + k0);
+        if (src + k0 + 16 <= dst && out.contiguous(src + k0, 16)) {  // 16 source bytes before the destination: one unaligned load
+          const u32x4 v = *reinterpret_cast<const AX_GLOBAL u32x4_u*>(out.at(src + k0));
 #pragma unroll
           for (uint32_t q = 0; q < 16; ++q)
             if (k0 + q < len) tile[drel + k0 + q] = uint8_t(v[q >> 2] >> (8 * (q & 3)));
@@ -1306,7 +1349,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
         }
         uint8_t v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = (k0 + q < len) ? out[src + idx[q]] : uint8_t(0);
+        for (int q = 0; q < 16; ++q) v[q] = (k0 + q < len) ? *out.at(src + idx[q]) : uint8_t(0);
 #pragma unroll
         for (int q = 0; q < 16; ++q)
           if (k0 + q < len) tile[drel + k0 + q] = v[q];
@@ -1323,7 +1366,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       const uint32_t step = 64 % dd;
       uint32_t j = lane % dd;
       for (uint32_t k = lane; k < n0; k += 64) {
-        tile[d0 + k] = out[s0 + j];
+        tile[d0 + k] = *out.at(s0 + j);
         j += step;
         if (j >= dd) j -= dd;
       }
@@ -1333,9 +1376,9 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   for (uint32_t k = threadIdx.x; k < nchunk; k += kCopyThreads) {
     if (!((dirty[k >> 5] >> (k & 31)) & 1)) continue;
     if (k < full) {
-      *reinterpret_cast<AX_GLOBAL u32x4*>(out + bs + 16 * k) = *reinterpret_cast<const u32x4*>(tile + 16 * k);
+      *reinterpret_cast<AX_GLOBAL u32x4*>(ob + 16 * k) = *reinterpret_cast<const u32x4*>(tile + 16 * k);
     } else {
-      for (uint32_t i = 16 * k; i < blen; ++i) out[bs + i] = tile[i];
+      for (uint32_t i = 16 * k; i < blen; ++i) ob[i] = tile[i];
     }
   }
   if (a.mark != kMarkJump) return;
@@ -1350,7 +1393,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   for (uint32_t base = wb.tok; base < t1; base += kCopyThreads) {
     const uint32_t t = base + threadIdx.x, r = t - wb.tok;
     const bool pend = t < t1 && ((lft[r >> 5] >> (r & 31)) & 1);
-    mark_wave(a, pend, t, mst[threadIdx.x >> 6], row, item);
+    mark_wave<O>(a, pend, t, mst[threadIdx.x >> 6], row, item);
   }
   __syncthreads();
   uint32_t* const lm = reinterpret_cast<uint32_t*>(a.lmap) + uint64_t(item) * (a.S / 32);
@@ -1363,6 +1406,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
 // or all laid end to end over the lanes).  Same results and lists as
 // k_round0; the leftovers of a wave (64-aligned tokens) fall in one 64-token
 // group and so in one sublist.
+template <class O>
 __global__ __launch_bounds__(kCopyThreads) void k_round0_waves(CopyArgs a) {
   __shared__ FillStage stage[kCopyThreads / 64];
   __shared__ MarkStage mstage[kCopyThreads / 64];
@@ -1375,12 +1419,12 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0_waves(CopyArgs a) {
     const bool act = t < a.n_tok;
     uint64_t src = 0, dst = 0;
     uint32_t len = 0, lo = 0, cnt = 0;
-    gbytes out = nullptr;
+    O out(a.jobs[0]);
     if (act) {
       token_at(a.tok, t, src, dst, len);
       const WinBlock wb = a.wbl[a.tblk[t]];
       const JobDev& J = a.jobs[wb.job];
-      out = gp(J.out);
+      out = O(J);
       const uint64_t dist = dst - src;
       find_cover(a, wb, J.B, src, src + (dist < len ? dist : len), lo, cnt);
       a.cov[2 * t] = lo;
@@ -1400,7 +1444,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0_waves(CopyArgs a) {
     const bool left = act && !ready;
     if (a.mark) {
       if (left && a.mark == kMarkList) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
-      if (a.mark == kMarkJump) mark_wave(a, left, t, mstage[threadIdx.x >> 6], nullptr, 0);
+      if (a.mark == kMarkJump) mark_wave<O>(a, left, t, mstage[threadIdx.x >> 6], nullptr, 0);
       continue;
     }
     const uint64_t m = __ballot(left);
@@ -1417,6 +1461,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0_waves(CopyArgs a) {
 // Later rounds visit the previous round's leftovers.  Leftovers go to this
 // workgroup's sublist (counters spread over kSub addresses), or, in the last
 // round, to the bitmap of the persistent launch.
+template <class O>
 __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
   __shared__ FillStage stage[kCopyThreads / 64];
   __shared__ MarkStage mstage[kCopyThreads / 64];
@@ -1447,10 +1492,10 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     }
     uint64_t src = 0, dst = 0;
     uint32_t len = 0, lo = 0, cnt = 0;
-    gbytes out = nullptr;
+    O out(a.jobs[0]);
     if (act) {
       token_at(a.tok, t, src, dst, len);
-      out = token_out(a, t);
+      out = token_out<O>(a, t);
       lo = a.cov[2 * t];
       cnt = a.cov[2 * t + 1];
     }
@@ -1461,7 +1506,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     const bool left = act && !ready;
     if (a.mark) {
       if (left && a.mark == kMarkList) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
-      if (a.mark == kMarkJump) mark_wave(a, left, t, mstage[threadIdx.x >> 6], nullptr, 0);
+      if (a.mark == kMarkJump) mark_wave<O>(a, left, t, mstage[threadIdx.x >> 6], nullptr, 0);
       continue;
     }
     const uint64_t m = __ballot(left);
@@ -1477,6 +1522,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
 // Round 0's long tokens: one workgroup per token, sixteen bytes per thread
 // in flight; the token is marked done (round 0) once the whole group is
 // through.
+template <class O>
 __global__ __launch_bounds__(kCopyThreads) void k_long(CopyArgs a) {
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const uint32_t n = *a.long_cnt;
@@ -1485,7 +1531,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_long(CopyArgs a) {
     uint64_t src, dst;
     uint32_t len;
     token_at(a.tok, t, src, dst, len);
-    const gbytes out = token_out(a, t);
+    const O out = token_out<O>(a, t);
     const uint64_t dist = dst - src;
     const uint64_t step = dist > kCopyThreads ? kCopyThreads : kCopyThreads % uint32_t(dist);
     uint64_t j = dist > threadIdx.x ? threadIdx.x : threadIdx.x % uint32_t(dist);
@@ -1499,10 +1545,10 @@ __global__ __launch_bounds__(kCopyThreads) void k_long(CopyArgs a) {
       }
       uint8_t v[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = (k0 + kCopyThreads * q < len) ? out[src + idx[q]] : uint8_t(0);
+      for (int q = 0; q < 16; ++q) v[q] = (k0 + kCopyThreads * q < len) ? *out.at(src + idx[q]) : uint8_t(0);
 #pragma unroll
       for (int q = 0; q < 16; ++q)
-        if (k0 + kCopyThreads * q < len) out[dst + k0 + kCopyThreads * q] = v[q];
+        if (k0 + kCopyThreads * q < len) *out.at(dst + k0 + kCopyThreads * q) = v[q];
     }
     __syncthreads();
     if (threadIdx.x == 0) a.done[t] = 0;
@@ -1573,6 +1619,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_pscatter(const uint32_t* pbits
 // each done flag, so a flag seen by another XCD implies its bytes are visible
 // there.  A token waits only on lower-indexed tokens, which are done or sit
 // in lower chunks whose tickets running waves hold, so every wait ends.
+template <class O>
 __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
   __shared__ FillStage stage[kCopyThreads / 64];
   const uint32_t lane = lane_id();
@@ -1594,10 +1641,10 @@ __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
       if (!__ballot(pending)) continue;
       uint64_t src = 0, dst = 0;
       uint32_t len = 0, lo = 0, cnt = 0;
-      gbytes out = nullptr;
+      O out(a.jobs[0]);
       if (pending) {
         token_at(a.tok, t, src, dst, len);
-        out = token_out(a, t);
+        out = token_out<O>(a, t);
         lo = a.cov[2 * t];
         cnt = a.cov[2 * t + 1];
       }
@@ -1695,6 +1742,7 @@ __device__ inline uint32_t jump_broken(DevStatus* st, uint32_t where) {
 
 // Before the bulk rounds: the leftover map starts empty (the last round sets
 // its bits) and every window block records where its output bytes start.
+template <class O>
 __global__ __launch_bounds__(kCopyThreads) void k_jprep(JumpArgs a) {
   const uint64_t words = uint64_t(a.n_items) * (a.S / 64);
   for (uint64_t g = uint64_t(blockIdx.x) * kCopyThreads + threadIdx.x; g < words;
@@ -1703,12 +1751,13 @@ __global__ __launch_bounds__(kCopyThreads) void k_jprep(JumpArgs a) {
   for (uint32_t x = blockIdx.x * kCopyThreads + threadIdx.x; x < a.n_items; x += gridDim.x * kCopyThreads) {
     const WinBlock wb = a.wbl[x];
     const JobDev& jd = a.jobs[wb.job];
-    a.ibase[x] = jd.out + wb.b * jd.B;
+    a.ibase[x] = (uint8_t*)(O(jd).at(wb.b * jd.B));
   }
 }
 
 // Long pending tokens: one wave per token, eight bytes per lane (first
 // entries as in the marking of a round, bits by global atomics).
+template <class O>
 __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
   __shared__ uint32_t sub_end[kSub];  // inclusive prefix of the sublist lengths
   if (jump_failed(a.st)) return;
@@ -1746,7 +1795,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
       for (uint32_t k = k0; k < k0 + kJMarkBytes && k < len; ++k) {
         const uint64_t sp = src + j, sb = sp >> lb;
         if (sb != cb) cb = sb, cin = window_block(a.wbl, a.S, wb, sb, cbase);
-        const uint32_t v = cin ? cbase + uint32_t(sp & (jd.B - 1)) : kJRes | gp(jd.out)[sp];
+        const uint32_t v = cin ? cbase + uint32_t(sp & (jd.B - 1)) : kJRes | *O(jd).at(sp);
         const uint32_t d = item * a.S + uint32_t(dst - bs) + k;
         J[d] = v;
         if ((d >> 5) != mw) {
@@ -2015,6 +2064,13 @@ __global__ __launch_bounds__(kCopyThreads) void k_jgather(JumpArgs a) {
   });
 }
 
+// A range decode's slot table: the window's blocks (one window) take slots
+// 0, 1, ... in window order.
+__global__ void k_slots(uint32_t* slot, const WinBlock* wbl, uint32_t n_items) {
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n_items; x += gridDim.x * blockDim.x)
+    slot[wbl[x].b] = x;
+}
+
 // Zero two word ranges (one launch for both).
 __global__ void k_clear2(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
@@ -2092,6 +2148,7 @@ struct Plan {
   hipEvent_t jfed = nullptr;     // h_jused is complete after this
   bool jfeed_pending = false, jsettled = false;
   bool learn = true;             // plans rebuilt for every call (ranges) keep the bound
+  bool mapped = false;           // one job whose output is a compact scratch addressed by slot
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
   void* graph_work = nullptr;
@@ -2133,9 +2190,14 @@ static Layout make_layout(const Plan& P) {
   L.done = at, at = align256(at + T);
   L.counts = at, at = align256(at + 4ull * 3 * kSub * kCounterStride);
   L.jflags = at, at = align256(at + 4ull * kJPasses * kJShards * kJFlagStride);  // cleared with the counters
-  // a workgroup appends at most what it visits: ceil(T / kSub) plus one
-  // launch-wide stride of slack per sublist
-  L.sub_cap = (T + kSub - 1) / kSub + uint64_t(kCopyThreads) * ((kMaxRoundGrid + kSub - 1) / kSub + 1);
+  // a round over n <= T items launches G = min(ceil(T / 256), kMaxRoundGrid)
+  // workgroups, each visiting at most ceil(n / (256 G)) * 256 items, and
+  // sublist s takes the items of the ceil(G / kSub) workgroups g = s mod kSub:
+  // at most n / kSub + 4 G + n / G + 256 <= ceil(T / kSub) + 256 (ceil(G /
+  // kSub) + 2) (leftovers filed by token group, (t / 64) mod kSub, stay
+  // within ceil(T / kSub) + 64)
+  const uint64_t G = std::min<uint64_t>((T + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid);
+  L.sub_cap = (T + kSub - 1) / kSub + uint64_t(kCopyThreads) * ((G + kSub - 1) / kSub + 2);
   L.list0 = at, at = align256(at + 4 * kSub * L.sub_cap);
   L.list1 = at, at = align256(at + 4 * kSub * L.sub_cap);
   L.llist = at, at = align256(at + 4 * T);
@@ -2190,6 +2252,8 @@ static int build_tables(Plan* P, const std::vector<JobSpec>& specs) {
       J.nb = I.n_blocks;
       J.B = I.block_size;
       J.mm = I.min_match;
+      J.slot = specs[j].slot;
+      J.junk = specs[j].junk;
       P->slot_b = std::max(P->slot_b, I.block_size);
       P->off_cap = std::max(P->off_cap, uint32_t((10 * (I.block_size / I.min_match + 1) + 15) & ~15u));
       P->len_cap = std::max(P->len_cap, 3 * I.block_size);
@@ -2243,6 +2307,7 @@ static int build_tables(Plan* P, const std::vector<JobSpec>& specs) {
       }
     }
     close();
+    P->mapped = !specs.empty() && specs[0].slot != nullptr;
     P->jpass.assign(P->wins.size(), 0);
     for (size_t i = 0; i < P->wins.size(); ++i) P->jpass[i] = jump_pass_bound(P->wins[i].tok);
     P->jsettled = false;
@@ -2290,7 +2355,7 @@ static int device_setup(Plan* P) {
   int dev = 0, cus = 0, occ = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_tail), kCopyThreads, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_tail<OutDirect>), kCopyThreads, 0);
   P->copy_grid = std::max(1, cus) * std::max(1, occ);
   return AX_OK;
 }
@@ -2359,6 +2424,15 @@ uint64_t plan_workspace_for(const aceapex_decoder* d, uint64_t max_blocks, uint6
 }
 
 void plan_copy_options(Plan* dst, const Plan* src) { dst->opt = src->opt; }
+
+int plan_set_slots(Plan* P, uint32_t* slot, hipStream_t s) {
+  if (P->wins.size() > 1) return fail(AX_E_CAPACITY, "a mapped plan holds one window");
+  if (P->wins.empty()) return AX_OK;
+  const uint32_t n = P->wins[0].items;
+  hipLaunchKernelGGL(k_slots, dim3((n + 255) / 256), dim3(256), 0, s, slot, P->d_wbl, n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? AX_OK : hip_fail(e, "slot table");
+}
 void plan_set_learn(Plan* P, bool learn) { P->learn = learn; }
 
 int plan_parse_tokens(Plan* P, void* d_work, uint64_t work_len, hipStream_t s, uint64_t* src, uint64_t* dstlen) {
@@ -2383,8 +2457,8 @@ int plan_parse_tokens(Plan* P, void* d_work, uint64_t work_len, hipStream_t s, u
     hipLaunchKernelGGL(k_ans, dim3(4 * W.items), dim3(64), 0, s, aa);
     ParseArgs pa{P->d_jobs, wbl, W.items, W.tok, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                  P->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), reinterpret_cast<uint64_t*>(w + L.tok),
-                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st};
-    hipLaunchKernelGGL(k_parse, dim3(W.items), dim3(kParseThreads), 0, s, pa);
+                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st, 0};
+    hipLaunchKernelGGL(k_parse<OutDirect>, dim3(W.items), dim3(kParseThreads), 0, s, pa);
     try {
       tk.resize(2ull * W.tok);
     } catch (const std::bad_alloc&) {
@@ -2520,7 +2594,8 @@ int plan_stage_ms(Plan* P, float* ans, float* parse, float* copy, float* remaind
 }
 
 // Enqueue the plan's kernels on s (also used inside a graph capture).
-static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool timed, bool feedback) {
+template <class O>
+static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool timed, bool feedback) {
   const Layout& L = P->lay;
   DevStatus* st = reinterpret_cast<DevStatus*>(w + L.status);
   if (P->wins.empty()) hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st, 1);  // status only
@@ -2538,8 +2613,8 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
     if (ev) (void)hipEventRecord(ev[1], s);
     ParseArgs pa{P->d_jobs, wbl, W.items, W.tok, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                  P->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), reinterpret_cast<uint64_t*>(w + L.tok),
-                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st};
-    hipLaunchKernelGGL(k_parse, dim3(W.items), dim3(kParseThreads), 0, s, pa);
+                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st, 1};
+    hipLaunchKernelGGL(k_parse<O>, dim3(W.items), dim3(kParseThreads), 0, s, pa);
     if (ev) (void)hipEventRecord(ev[2], s);
     const uint32_t ntok = W.tok;
     const bool jump = P->opt.tail_mode == 0 && copy_mode != AX_COPY_SERIAL;
@@ -2571,11 +2646,11 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
       const uint64_t mwords = uint64_t(W.items) * (P->slot_b / 64);  // leftover-map words
       // eight listed words per wave step, four waves per workgroup
       const uint32_t jgrid = uint32_t(std::min<uint64_t>((mwords + 31) / 32, kJMaxGrid));
-      if (jump) hipLaunchKernelGGL(k_jprep, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
+      if (jump) hipLaunchKernelGGL(k_jprep<O>, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
       const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
-      if (P->opt.round0_tile) hipLaunchKernelGGL(k_round0, dim3(W.items), dim3(kCopyThreads), 0, s, ca);
-      else hipLaunchKernelGGL(k_round0_waves, dim3(grid), dim3(kCopyThreads), 0, s, ca);
-      hipLaunchKernelGGL(k_long, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
+      if (P->opt.round0_tile) hipLaunchKernelGGL(k_round0<O>, dim3(W.items), dim3(kCopyThreads), 0, s, ca);
+      else hipLaunchKernelGGL(k_round0_waves<O>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
+      hipLaunchKernelGGL(k_long<O>, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
       for (int r = 1; r < P->opt.bulk_rounds; ++r) {
         ca.round = uint32_t(r);
         ca.list_in = lists[(r - 1) & 1];
@@ -2585,7 +2660,7 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
         ca.cnt_clear = cset(r + 1);
         ca.mark = r + 1 == P->opt.bulk_rounds ? last_mark : 0;
         // later rounds see the previous round's leftovers only
-        hipLaunchKernelGGL(k_round, dim3(grid), dim3(kCopyThreads), 0, s, ca);
+        hipLaunchKernelGGL(k_round<O>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       }
       ca.round = uint32_t(P->opt.bulk_rounds);
       if (ev) (void)hipEventRecord(ev[3], s);
@@ -2600,7 +2675,7 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
         // list the map's busy words, settle the first entries, jump, write
         ja.llist = ca.list_out;  // the last round's output sublists hold the long pending tokens
         ja.lcnt = ca.cnt_out;
-        hipLaunchKernelGGL(k_jmarklong, dim3(grid), dim3(kCopyThreads), 0, s, ja);
+        hipLaunchKernelGGL(k_jmarklong<O>, dim3(grid), dim3(kCopyThreads), 0, s, ja);
         const uint32_t lgrid = uint32_t((mwords + kJListWords - 1) / kJListWords);
         hipLaunchKernelGGL(k_jlcount, dim3(lgrid), dim3(kCopyThreads), 0, s, ja);
         hipLaunchKernelGGL(k_jlist, dim3(lgrid), dim3(kCopyThreads), 0, s, ja);
@@ -2615,12 +2690,18 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
       } else {
         const uint64_t waves = (ntok + 64ull * P->opt.tail_chunks - 1) / (64ull * P->opt.tail_chunks);
         const uint32_t tgrid = uint32_t(std::min<uint64_t>((waves + 3) / 4, uint64_t(P->copy_grid)));
-        hipLaunchKernelGGL(k_tail, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);
+        hipLaunchKernelGGL(k_tail<O>, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);
       }
     }
     if (ev && !ntok) (void)hipEventRecord(ev[3], s);
     if (ev) (void)hipEventRecord(ev[4], s);
   }
+}
+
+// The launch sequence for the plan's output addressing.
+static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool timed, bool feedback) {
+  if (P->mapped) enqueue_out<OutMapped>(P, w, copy_mode, s, timed, feedback);
+  else enqueue_out<OutDirect>(P, w, copy_mode, s, timed, feedback);
 }
 
 int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s) {
@@ -2795,6 +2876,7 @@ int aceapex_decoder_create(const uint8_t* h, uint64_t h_len, const uint8_t* d_ar
 
 void aceapex_decoder_destroy(aceapex_decoder* d) {
   if (!d) return;
+  aceapex_range_plan_destroy(d->range);
   ax::plan_destroy(d->plan);
   delete d;
 }

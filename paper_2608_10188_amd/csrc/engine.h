@@ -25,11 +25,16 @@ struct PlanOptions {
 };
 
 // One archive to decode: all blocks (blocks empty) or the listed blocks
-// (ascending).  Its bytes land in out at their absolute positions.
+// (ascending).  Its bytes land in out at their absolute positions, or, when
+// slot is set (a plan of one job and one window), block b's bytes at
+// out + slot[b] * B with the listed blocks in slots 0, 1, ... (plan_set_slots
+// writes those entries) and any slot >= junk meaning the junk block.
 struct JobSpec {
   const aceapex_decoder* dec;
   uint8_t* out;
   std::vector<uint64_t> blocks;
+  uint32_t* slot = nullptr;
+  uint32_t junk = 0;
 };
 
 // Window limits: a window's workspace is about 130 KiB per block plus 45 B per
@@ -45,11 +50,14 @@ int plan_reset(Plan* p, const std::vector<JobSpec>& jobs, hipStream_t s);
 // Workspace of a one-window plan of decoder d with these maxima.
 uint64_t plan_workspace_for(const aceapex_decoder* d, uint64_t max_blocks, uint64_t max_tokens);
 void plan_copy_options(Plan* dst, const Plan* src);
+// Enqueue the slot-table entries of a mapped plan's blocks on s.
+int plan_set_slots(Plan* p, uint32_t* slot, hipStream_t s);
 // Whether a plan learns its jump-pass counts from its own decodes (on by
 // default; off for plans rebuilt for every call).
 void plan_set_learn(Plan* p, bool learn);
-// Entropy + parse only, every window; the match tokens (src; dst | (len-1)
-// << 48) are copied to host arrays in archive order.  Synchronous.
+// Entropy + parse only, every window, writing no output bytes; the match
+// tokens (src; dst | (len-1) << 48) are copied to host arrays in archive
+// order.  Synchronous.
 int plan_parse_tokens(Plan* p, void* d_work, uint64_t work_len, hipStream_t s, uint64_t* src, uint64_t* dstlen);
 void plan_destroy(Plan* p);
 uint64_t plan_workspace(const Plan* p);
@@ -74,4 +82,5 @@ struct aceapex_decoder {
   uint64_t arc_len = 0;
   ax::Plan* plan = nullptr;
   std::vector<uint64_t> idx_src, idx_dstlen;  // token index (aceapex_decoder_build_index)
+  aceapex_range_plan* range = nullptr;        // aceapex_decode_range's plan (created on first use)
 };

@@ -159,23 +159,35 @@ int union_closure(const aceapex_decoder* d, uint32_t n, const uint64_t* offs, co
   return AX_OK;
 }
 
-// Copy range bytes from the full-size scratch output to each caller buffer.
-// Every range is cut into 4 KiB chunks numbered across the batch (chunk0 is a
-// range's first chunk); a workgroup copies one chunk, each thread sixteen
-// bytes with all loads issued before the stores, so wide ranges spread over
-// the whole device and every byte instruction of a wave covers 64
-// consecutive bytes.  Source and destination alignments are arbitrary.
+// Copy range bytes from the compact scratch to each caller buffer.  Byte p
+// of the archive lives at scratch + slot[p / B] * B + p mod B (the range's
+// blocks are all in the plan, so their slots are set).  Every range is cut
+// into 4 KiB chunks numbered across the batch (chunk0 is a range's first
+// chunk); a workgroup copies one chunk, each thread sixteen bytes with all
+// loads issued before the stores, so wide ranges spread over the whole
+// device and every byte instruction of a wave covers 64 consecutive bytes.
+// Destination alignments are arbitrary.
 constexpr uint32_t kGatherThreads = 256;
 constexpr uint32_t kGatherChunk = 16 * kGatherThreads;
 
 struct GatherDesc {
-  const uint8_t* src;
+  uint64_t off;  // archive position of the range's first byte
   uint8_t* dst;
   uint64_t len;
   uint64_t chunk0;
 };
 
-__global__ __launch_bounds__(kGatherThreads) void k_gather(const GatherDesc* desc, uint32_t n, uint64_t chunks) {
+struct ScratchMap {
+  const uint8_t* base;
+  const uint32_t* slot;
+  uint32_t lb, junk;
+};
+
+__global__ __launch_bounds__(kGatherThreads) void k_gather(const GatherDesc* desc, uint32_t n, uint64_t chunks,
+                                                           ScratchMap m) {
+  typedef const __attribute__((address_space(1))) uint8_t* cgbytes;
+  const __attribute__((address_space(1))) uint32_t* slot = (const __attribute__((address_space(1))) uint32_t*)m.slot;
+  const uint64_t bmask = (1ull << m.lb) - 1;
   for (uint64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
     uint32_t lo = 0, hi = n - 1;  // last range whose first chunk is <= c
     while (lo < hi) {
@@ -183,14 +195,20 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const GatherDesc* des
       if (desc[mid].chunk0 <= c) lo = mid; else hi = mid - 1;
     }
     const GatherDesc g = desc[lo];
-    const __attribute__((address_space(1))) uint8_t* src = (const __attribute__((address_space(1))) uint8_t*)g.src;
     __attribute__((address_space(1))) uint8_t* dst = (__attribute__((address_space(1))) uint8_t*)g.dst;
     const uint64_t base = (c - g.chunk0) * kGatherChunk + threadIdx.x;
     uint8_t v[16];
 #pragma unroll
     for (uint32_t q = 0; q < 16; ++q) {
       const uint64_t k = base + q * kGatherThreads;
-      v[q] = k < g.len ? src[k] : uint8_t(0);
+      if (k < g.len) {
+        const uint64_t p = g.off + k;
+        uint32_t x = slot[p >> m.lb];
+        if (x >= m.junk) x = m.junk;
+        v[q] = ((cgbytes)m.base)[(uint64_t(x) << m.lb) + (p & bmask)];
+      } else {
+        v[q] = 0;
+      }
     }
 #pragma unroll
     for (uint32_t q = 0; q < 16; ++q) {
@@ -200,15 +218,32 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const GatherDesc* des
   }
 }
 
+// Workspace of a range decode whose closure is at most `blocks` blocks and
+// `tokens` matches: the plan's workspace, the compact scratch ((blocks + 1)
+// blocks: the last is the junk block) and the slot table (one u32 per
+// archive block), each 256-byte aligned.
+struct RangeLayout {
+  uint64_t plan, scratch_at, slot_at, total;
+};
+RangeLayout range_layout(const aceapex_decoder* d, uint64_t blocks, uint64_t tokens) {
+  RangeLayout L;
+  const uint64_t B = d->info.block_size;
+  L.plan = ax::plan_workspace_for(d, blocks, tokens);
+  L.scratch_at = (L.plan + 255) & ~255ull;
+  L.slot_at = (L.scratch_at + (blocks + 1) * B + 255) & ~255ull;
+  L.total = L.slot_at + 4 * std::max<uint64_t>(1, d->info.n_blocks);
+  return L;
+}
+
 }  // namespace
 
-// A reusable range-decode plan: the decoder, capacity limits, and the plan of
-// the current block set.
+// A reusable range-decode plan: the decoder, capacity limits, the plan of
+// the current closure and the pinned staging of the gather descriptors.
 struct aceapex_range_plan {
   aceapex_decoder* dec = nullptr;
   uint64_t max_blocks = 0, max_tokens = 0;
   ax::Plan* plan = nullptr;          // rebuilt per call
-  uint64_t workspace = 0;            // for max_blocks / max_tokens
+  RangeLayout lay{};                 // for max_blocks / max_tokens
   GatherDesc* d_desc = nullptr;
   GatherDesc* h_desc = nullptr;
   uint32_t desc_cap = 0;
@@ -225,10 +260,91 @@ struct aceapex_range_plan {
   }
 };
 
+namespace {
+
+// Decode the union closure of n ranges with a range plan into its compact
+// scratch and gather each range to its output (everything after the host
+// closure is asynchronous on s).
+// Closures of fewer matches finish their deep remainder with the persistent
+// chase (few launches; their chains are short), larger ones by pointer
+// jumping (a deep closure's chains are long).
+constexpr uint64_t kRangeJumpTokens = 1u << 16;
+
+int run_ranges(aceapex_range_plan* rp, const RangeLayout& lay, uint32_t n, const uint64_t* offs,
+               const uint64_t* lens, uint8_t* const* d_outs, const uint64_t* out_caps, void* d_work,
+               uint64_t work_len, int copy_mode, hipStream_t s, std::vector<uint64_t>* closure) {
+  aceapex_decoder* d = rp->dec;
+  if (!d_work) return ax::fail(AX_E_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(d_work) & 255) return ax::fail(AX_E_ARG, "workspace must be 256-byte aligned");
+  if (work_len < lay.total) return ax::fail(AX_E_CAPACITY, "workspace too small");
+  for (uint32_t i = 0; i < n; ++i) {
+    if (lens[i] && !d_outs[i]) return ax::fail(AX_E_ARG, "null output");
+    if (out_caps[i] < lens[i]) return ax::fail(AX_E_CAPACITY, "output smaller than its range");
+  }
+  std::vector<uint64_t> bl;
+  int rc = AX_OK;
+  if (closure) bl.swap(*closure);  // computed by the caller
+  else rc = union_closure(d, n, offs, lens, bl, 0);
+  if (rc) return rc;
+  uint64_t tok = 0;
+  for (uint64_t b : bl) tok += d->mpre[b + 1] - d->mpre[b];
+  if (bl.size() > rp->max_blocks || tok > rp->max_tokens)
+    return ax::fail(AX_E_CAPACITY, "closure larger than the plan's capacity");
+  rp->last_blocks = bl.size();
+  rp->last_tokens = tok;
+  uint8_t* const w = static_cast<uint8_t*>(d_work);
+  uint8_t* const scratch = w + lay.scratch_at;
+  uint32_t* const slot = reinterpret_cast<uint32_t*>(w + lay.slot_at);
+  // the previous call's uploads must be through before staging is rewritten
+  (void)hipEventSynchronize(rp->upload_done);
+  if (!bl.empty()) {
+    ax::JobSpec js{d, scratch, std::move(bl), slot, uint32_t(rp->max_blocks)};
+    if (!rp->plan) {
+      rc = ax::plan_create({js}, &rp->plan);
+      if (!rc) ax::plan_set_learn(rp->plan, false);
+    } else {
+      rc = ax::plan_reset(rp->plan, {js}, s);
+    }
+    if (rc) return rc;
+    ax::plan_copy_options(rp->plan, d->plan);
+    rc = ax::plan_set_option(rp->plan, AX_OPT_TAIL_MODE, tok >= kRangeJumpTokens ? 0 : 1);
+    if (!rc) rc = ax::plan_set_slots(rp->plan, slot, s);
+    if (!rc) rc = ax::plan_run(rp->plan, d_work, lay.plan, copy_mode, s);
+    if (rc) return rc;
+  }
+  if (n) {
+    if (n > rp->desc_cap) {
+      if (rp->d_desc) (void)hipFree(rp->d_desc), rp->d_desc = nullptr;
+      if (rp->h_desc) (void)hipHostFree(rp->h_desc), rp->h_desc = nullptr;
+      rp->desc_cap = std::max<uint32_t>(n, 2 * rp->desc_cap);
+      hipError_t e = hipMalloc(reinterpret_cast<void**>(&rp->d_desc), sizeof(GatherDesc) * rp->desc_cap);
+      if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&rp->h_desc), sizeof(GatherDesc) * rp->desc_cap);
+      if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
+    }
+    uint64_t chunks = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      rp->h_desc[i] = GatherDesc{offs[i], d_outs[i], lens[i], chunks};
+      chunks += (lens[i] + kGatherChunk - 1) / kGatherChunk;
+    }
+    hipError_t e = hipMemcpyAsync(rp->d_desc, rp->h_desc, sizeof(GatherDesc) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
+    const ScratchMap m{scratch, slot, uint32_t(__builtin_ctz(d->info.block_size)), uint32_t(rp->max_blocks)};
+    if (chunks)
+      hipLaunchKernelGGL(k_gather, dim3(uint32_t(std::min<uint64_t>(chunks, 8192))), dim3(kGatherThreads), 0, s,
+                         rp->d_desc, n, chunks, m);
+    e = hipGetLastError();
+    if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
+  }
+  (void)hipEventRecord(rp->upload_done, s);
+  return AX_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-int aceapex_decoder_build_index(aceapex_decoder* d, uint8_t* d_full, void* d_work, uint64_t work_len, void* stream) {
-  if (!d || !d_full || !d_work) return ax::fail(AX_E_ARG, "null argument");
+int aceapex_decoder_build_index(aceapex_decoder* d, void* d_work, uint64_t work_len, void* stream) {
+  if (!d || !d_work) return ax::fail(AX_E_ARG, "null argument");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   try {
     d->idx_src.assign(d->info.n_matches, 0);
@@ -236,7 +352,6 @@ int aceapex_decoder_build_index(aceapex_decoder* d, uint8_t* d_full, void* d_wor
   } catch (const std::bad_alloc&) {
     return ax::fail(AX_E_NOMEM, "token index");
   }
-  ax::plan_set_out(d->plan, 0, d_full);
   return ax::plan_parse_tokens(d->plan, d_work, work_len, s, d->idx_src.data(), d->idx_dstlen.data());
 }
 
@@ -270,7 +385,7 @@ int aceapex_range_plan_create(aceapex_decoder* d, uint64_t max_blocks, uint64_t 
   rp->dec = d;
   rp->max_blocks = max_blocks;
   rp->max_tokens = max_tokens;
-  rp->workspace = ax::plan_workspace_for(d, max_blocks, max_tokens);
+  rp->lay = range_layout(d, max_blocks, max_tokens);
   if (hipEventCreateWithFlags(&rp->upload_done, hipEventDisableTiming) != hipSuccess) {
     delete rp;
     return ax::fail(AX_E_HIP, "event");
@@ -283,7 +398,7 @@ void aceapex_range_plan_destroy(aceapex_range_plan* rp) { delete rp; }
 
 int aceapex_range_plan_workspace(const aceapex_range_plan* rp, uint64_t* bytes) {
   if (!rp || !bytes) return ax::fail(AX_E_ARG, "null argument");
-  *bytes = rp->workspace;
+  *bytes = rp->lay.total;
   return AX_OK;
 }
 
@@ -295,65 +410,50 @@ int aceapex_range_plan_last(const aceapex_range_plan* rp, uint64_t* blocks, uint
 }
 
 int aceapex_decode_ranges(aceapex_range_plan* rp, uint32_t n, const uint64_t* offs, const uint64_t* lens,
-                          uint8_t* const* d_outs, uint8_t* d_full, void* d_work, uint64_t work_len, int copy_mode,
-                          void* stream) {
-  if (!rp || (n && (!offs || !lens || !d_outs)) || !d_full || !d_work) return ax::fail(AX_E_ARG, "null argument");
-  if (work_len < rp->workspace) return ax::fail(AX_E_CAPACITY, "workspace too small");
-  aceapex_decoder* d = rp->dec;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+                          uint8_t* const* d_outs, const uint64_t* out_caps, void* d_work, uint64_t work_len,
+                          int copy_mode, void* stream) {
+  if (!rp || (n && (!offs || !lens || !d_outs || !out_caps))) return ax::fail(AX_E_ARG, "null argument");
+  return run_ranges(rp, rp->lay, n, offs, lens, d_outs, out_caps, d_work, work_len, copy_mode,
+                    reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+int aceapex_range_workspace(const aceapex_decoder* d, uint64_t off, uint64_t len, uint64_t* bytes) {
+  if (!d || !bytes) return ax::fail(AX_E_ARG, "null argument");
   std::vector<uint64_t> bl;
-  int rc = union_closure(d, n, offs, lens, bl, 0);
+  int rc = len ? union_closure(d, 1, &off, &len, bl, 1) : AX_OK;
   if (rc) return rc;
   uint64_t tok = 0;
   for (uint64_t b : bl) tok += d->mpre[b + 1] - d->mpre[b];
-  if (bl.size() > rp->max_blocks || tok > rp->max_tokens)
-    return ax::fail(AX_E_CAPACITY, "closure larger than the plan's capacity");
-  rp->last_blocks = bl.size();
-  rp->last_tokens = tok;
-  // the previous call's uploads must be through before staging is rewritten
-  (void)hipEventSynchronize(rp->upload_done);
-  if (!bl.empty()) {
-    if (!rp->plan) {
-      rc = ax::plan_create({ax::JobSpec{d, d_full, std::move(bl)}}, &rp->plan);
-      if (!rc) ax::plan_set_learn(rp->plan, false);
-    } else {
-      rc = ax::plan_reset(rp->plan, {ax::JobSpec{d, d_full, std::move(bl)}}, s);
-    }
-    if (rc) return rc;
-    ax::plan_copy_options(rp->plan, d->plan);
-    rc = ax::plan_run(rp->plan, d_work, work_len, copy_mode, s);
-    if (rc) return rc;
-  }
-  if (n) {
-    if (n > rp->desc_cap) {
-      if (rp->d_desc) (void)hipFree(rp->d_desc), rp->d_desc = nullptr;
-      if (rp->h_desc) (void)hipHostFree(rp->h_desc), rp->h_desc = nullptr;
-      rp->desc_cap = std::max<uint32_t>(n, 2 * rp->desc_cap);
-      hipError_t e = hipMalloc(reinterpret_cast<void**>(&rp->d_desc), sizeof(GatherDesc) * rp->desc_cap);
-      if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&rp->h_desc), sizeof(GatherDesc) * rp->desc_cap);
-      if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
-    }
-    uint64_t chunks = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-      rp->h_desc[i] = GatherDesc{d_full + offs[i], d_outs[i], lens[i], chunks};
-      chunks += (lens[i] + kGatherChunk - 1) / kGatherChunk;
-    }
-    hipError_t e = hipMemcpyAsync(rp->d_desc, rp->h_desc, sizeof(GatherDesc) * n, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
-    if (chunks)
-      hipLaunchKernelGGL(k_gather, dim3(uint32_t(std::min<uint64_t>(chunks, 8192))), dim3(kGatherThreads), 0, s,
-                         rp->d_desc, n, chunks);
-    e = hipGetLastError();
-    if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
-  }
-  (void)hipEventRecord(rp->upload_done, s);
+  if (bl.size() > ax::kWindowBlocks || tok > ax::kWindowTokens)
+    return ax::fail(AX_E_CAPACITY, "closure larger than one window");
+  *bytes = range_layout(d, std::max<uint64_t>(1, bl.size()), tok).total;
   return AX_OK;
 }
 
-int aceapex_decode_range(aceapex_range_plan* rp, uint64_t off, uint64_t len, uint8_t* d_out, uint8_t* d_full,
+int aceapex_decode_range(aceapex_decoder* d, uint64_t off, uint64_t len, uint8_t* d_out, uint64_t out_cap,
                          void* d_work, uint64_t work_len, void* stream) {
+  if (!d) return ax::fail(AX_E_ARG, "null decoder");
+  if (!d->range) {
+    aceapex_range_plan* rp = nullptr;
+    int rc = aceapex_range_plan_create(d, ax::kWindowBlocks, ax::kWindowTokens, &rp);
+    if (rc) return rc;
+    d->range = rp;
+  }
+  std::vector<uint64_t> bl;
+  int rc = len ? union_closure(d, 1, &off, &len, bl, 1) : AX_OK;
+  if (rc) return rc;
+  uint64_t tok = 0;
+  for (uint64_t b : bl) tok += d->mpre[b + 1] - d->mpre[b];
+  if (bl.size() > ax::kWindowBlocks || tok > ax::kWindowTokens)
+    return ax::fail(AX_E_CAPACITY, "closure larger than one window");
+  // the workspace this range needs (aceapex_range_workspace), laid out for its own closure
+  const RangeLayout lay = range_layout(d, std::max<uint64_t>(1, bl.size()), tok);
+  aceapex_range_plan* rp = d->range;
+  rp->max_blocks = std::max<uint64_t>(1, bl.size());
+  rp->max_tokens = tok;
   uint8_t* outs[1] = {d_out};
-  return aceapex_decode_ranges(rp, 1, &off, &len, outs, d_full, d_work, work_len, AX_COPY_PERIODIC, stream);
+  return run_ranges(rp, lay, 1, &off, &len, outs, &out_cap, d_work, work_len, AX_COPY_PERIODIC,
+                    reinterpret_cast<hipStream_t>(stream), &bl);
 }
 
 }  // extern "C"

@@ -1,17 +1,21 @@
 """Serving loop: random-access byte ranges against an archive held compressed
 in device memory, with continuous batching.
 
-Requests (offset, length) arrive on an open-loop schedule.  Whenever a slot
-is free, every request that has arrived and fits the slot's scratch limits
-(blocks and matches of the union source closure) is admitted into one batch,
-and the batch is decoded by the library on that slot's stream
+Requests (offset, length) arrive on an open-loop schedule.  Each slot owns a
+stream and one range-plan workspace sized by closure limits (blocks and
+matches of a batch's union source closure, plus a compact scratch of those
+blocks), so the device memory of serving is slots x workspace, independent of
+the archive's size.  A request's own closure size is computed once, when it
+arrives; whenever a slot is free, the requests that have arrived are
+admitted in arrival order while the sum of their closure sizes fits the
+slot's limits (the sum bounds the union, so an admitted batch always fits)
+and decoded as one batch by the library on that slot's stream
 (aceapex_decode_ranges: union closure on the host, plan upload, entropy,
 parse and match layer of the closure blocks, copy of each range to its
 output).  Requests that arrive while batches run join the next batch as a
-slot frees up, and batches on different slots overlap on the device.  Each
-slot owns its stream, workspace and a scratch output of the archive's size,
-so concurrent batches never write the same bytes.  Latency is arrival to
-completion, read from HIP events on the device timeline.
+slot frees up, and batches on different slots overlap on the device.
+Latency is arrival to completion, read from HIP events on the device
+timeline.
 """
 import collections
 import gc
@@ -19,7 +23,7 @@ import time
 
 import numpy as np
 
-from . import AX_E_CAPACITY, COPY_PERIODIC, AceapexError, Decoder, RangePlan
+from . import COPY_PERIODIC, Decoder, RangePlan
 
 
 class Server:
@@ -27,24 +31,29 @@ class Server:
         import torch
 
         self.dec = Decoder(h_archive, d_archive)
-        n = int(self.dec.info.n_bytes)
         dev = d_archive.device
+        self.dec.build_index()
+        self.dec._work = None  # the whole-archive workspace is only needed for the index
         self.slots = []
         for _ in range(slots):
-            full = torch.empty(max(16, n), dtype=torch.uint8, device=dev)
             plan = RangePlan(self.dec, max_blocks, max_tokens)
             work = torch.empty(max(256, plan.workspace_bytes), dtype=torch.uint8, device=dev)
-            self.slots.append({"full": full, "plan": plan, "work": work, "stream": torch.cuda.Stream(device=dev)})
-        self.dec.build_index(self.slots[0]["full"])
-        self.dec._work = None  # the whole-archive workspace is only needed for the index
+            self.slots.append({"plan": plan, "work": work, "stream": torch.cuda.Stream(device=dev)})
         torch.cuda.synchronize()
+        self.max_blocks, self.max_tokens = int(max_blocks), int(max_tokens)
+        self.workspace_bytes = sum(int(s["work"].numel()) for s in self.slots)
         self.max_batch = max_batch
         self.device = dev
 
+    def closure_size(self, off, length):
+        """(blocks, matches) of one range's source closure (host)."""
+        _, tokens, blocks = self.dec.closure_blocks([off], [length], threads=1, want_blocks=False)
+        return blocks, tokens
+
     def _launch(self, slot, ids, offs, lens, outs):
         s = self.slots[slot]
-        s["plan"].decode([int(offs[i]) for i in ids], [int(lens[i]) for i in ids], [outs[i] for i in ids], s["full"],
-                         s["work"], COPY_PERIODIC, stream=s["stream"])
+        s["plan"].decode([int(offs[i]) for i in ids], [int(lens[i]) for i in ids], [outs[i] for i in ids], s["work"],
+                         COPY_PERIODIC, stream=s["stream"])
 
     def run(self, arrivals_ns, offs, lens, outs, realtime=True, max_batch=None, slots=None):
         """Serve every request; outs[i] receives range i (a CUDA uint8 tensor
@@ -70,6 +79,7 @@ class Server:
         free = collections.deque(range(min(len(self.slots), slots or len(self.slots))))
         inflight = {}
         queue = collections.deque()
+        size = [None] * n  # closure (blocks, matches), computed on arrival
         done_ev = [None] * n
         host_done = np.zeros(n, np.int64)
         batch_sizes, batch_blocks = [], []
@@ -81,6 +91,9 @@ class Server:
         while completed < n:
             now = time.perf_counter_ns() - t0
             while nxt < n and (not realtime or arrivals[nxt] <= now):
+                size[nxt] = self.closure_size(int(offs[nxt]), int(lens[nxt]))
+                if size[nxt][0] > self.max_blocks or size[nxt][1] > self.max_tokens:
+                    raise ValueError(f"request {nxt}: closure {size[nxt]} exceeds a slot's limits")
                 queue.append(nxt)
                 nxt += 1
             for slot in list(inflight):
@@ -95,17 +108,16 @@ class Server:
             progressed = False
             while free and queue:
                 slot = free.popleft()
-                take = [queue[k] for k in range(min(len(queue), max_batch))]
-                while True:
-                    try:
-                        self._launch(slot, take, offs, lens, outs)
+                # admission by scratch: arrival order, while the summed
+                # closure sizes fit the slot's workspace limits
+                take, nb, nt = [], 0, 0
+                while queue and len(take) < max_batch:
+                    b, t = size[queue[0]]
+                    if take and (nb + b > self.max_blocks or nt + t > self.max_tokens):
                         break
-                    except AceapexError as e:  # admission by scratch: shrink the batch
-                        if e.code != AX_E_CAPACITY or len(take) == 1:
-                            raise
-                        take = take[: len(take) // 2]
-                for _ in take:
-                    queue.popleft()
+                    take.append(queue.popleft())
+                    nb, nt = nb + b, nt + t
+                self._launch(slot, take, offs, lens, outs)
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(self.slots[slot]["stream"])
                 for i in take:

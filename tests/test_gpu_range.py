@@ -1,6 +1,7 @@
 """GPU parity of random access: the library's byte-precise source closure
-against the oracle's, range decodes against the original bytes, and the
-serving loop's results alone and in the mix."""
+against the oracle's, range decodes (into a compact scratch sized by the
+closure) against the original bytes, capacity errors returned before any
+launch, and the serving loop's results alone and in the mix."""
 import numpy as np
 import pytest
 
@@ -28,9 +29,8 @@ def dna_archive():
 
 def _decoder_with_index(arc):
     d = ax.Decoder(arc, torch.from_numpy(arc).cuda())
-    full = torch.empty(max(16, int(d.info.n_bytes)), dtype=torch.uint8, device="cuda")
-    d.build_index(full)
-    return d, full
+    d.build_index()
+    return d
 
 
 def _ranges(n_bytes, count, seed):
@@ -51,7 +51,7 @@ def test_closure_matches_oracle(kind, dna_archive):
         x = synth.text(3 << 20, 62)
         arc, _ = oracle.encode(x)
     _say("closure", kind)
-    d, _ = _decoder_with_index(arc)
+    d = _decoder_with_index(arc)
     for off, ln in _ranges(x.size, 40, 7):
         mask, k = oracle.closure(arc, off, ln)
         blocks, ntok, nb = d.closure_blocks([off], [ln])
@@ -60,7 +60,7 @@ def test_closure_matches_oracle(kind, dna_archive):
 
 def test_union_closure_is_union(dna_archive):
     x, arc = dna_archive
-    d, _ = _decoder_with_index(arc)
+    d = _decoder_with_index(arc)
     rs = _ranges(x.size, 12, 8)
     union = set()
     for off, ln in rs:
@@ -71,16 +71,18 @@ def test_union_closure_is_union(dna_archive):
 
 def test_decode_ranges_match_original(dna_archive):
     x, arc = dna_archive
-    d, full = _decoder_with_index(arc)
+    d = _decoder_with_index(arc)
     rp = ax.RangePlan(d, max_blocks=512, max_tokens=1 << 18)
     work = torch.empty(rp.workspace_bytes, dtype=torch.uint8, device="cuda")
+    # the scratch is sized by the closure limits, not by the archive
+    assert rp.workspace_bytes < 600 * B * 160
     rs = _ranges(x.size, 30, 9)
     rs = [r for r in rs if r[1] <= 64 * B]
     for batch in (rs[:1], rs[:7], rs):
         _say("decode_ranges", len(batch))
         outs = [torch.full((max(1, ln),), 0xCC, dtype=torch.uint8, device="cuda") for _, ln in batch]
-        full.fill_(0xCC)
-        rp.decode([r[0] for r in batch], [r[1] for r in batch], outs, full, work)
+        work.fill_(0xCC)  # stale scratch and slot-table contents must not matter
+        rp.decode([r[0] for r in batch], [r[1] for r in batch], outs, work)
         err, bad = ax.workspace_status(work)
         assert err == 0, (err, bad)
         for (off, ln), o in zip(batch, outs):
@@ -91,7 +93,7 @@ def test_decode_ranges_into_unaligned_views(dna_archive):
     """Outputs that are views of one buffer at odd offsets (as a server packs
     them), ranges of 1 B to several 4 KiB gather chunks."""
     x, arc = dna_archive
-    d, full = _decoder_with_index(arc)
+    d = _decoder_with_index(arc)
     rp = ax.RangePlan(d, max_blocks=512, max_tokens=1 << 18)
     work = torch.empty(rp.workspace_bytes, dtype=torch.uint8, device="cuda")
     rng = np.random.default_rng(12)
@@ -100,7 +102,7 @@ def test_decode_ranges_into_unaligned_views(dna_archive):
     _say("unaligned views", len(lens))
     buf = torch.full((sum(lens) + 7,), 0xCC, dtype=torch.uint8, device="cuda")
     outs = list(torch.split(buf[7:], lens))
-    rp.decode(offs, lens, outs, full, work)
+    rp.decode(offs, lens, outs, work)
     got = buf.cpu().numpy()
     assert (got[:7] == 0xCC).all()
     at = 7
@@ -111,28 +113,70 @@ def test_decode_ranges_into_unaligned_views(dna_archive):
 
 def test_block_straddling_sweep(dna_archive):
     x, arc = dna_archive
-    d, full = _decoder_with_index(arc)
+    d = _decoder_with_index(arc)
     rp = ax.RangePlan(d, max_blocks=512, max_tokens=1 << 18)
     work = torch.empty(rp.workspace_bytes, dtype=torch.uint8, device="cuda")
     rs = [(b * B - k, 2 * k) for b in range(1, x.size // B) for k in (1, 7, 300)]
     _say("straddle", len(rs))
     outs = [torch.empty(ln, dtype=torch.uint8, device="cuda") for _, ln in rs]
     for i in range(0, len(rs), 64):
-        rp.decode([r[0] for r in rs[i:i + 64]], [r[1] for r in rs[i:i + 64]], outs[i:i + 64], full, work)
+        rp.decode([r[0] for r in rs[i:i + 64]], [r[1] for r in rs[i:i + 64]], outs[i:i + 64], work)
     torch.cuda.synchronize()
     for (off, ln), o in zip(rs, outs):
         assert np.array_equal(o.cpu().numpy(), x[off:off + ln])
 
 
-def test_capacity_limit_is_reported(dna_archive):
+def test_capacity_errors_before_any_launch(dna_archive):
+    """A closure above the plan's limits, an output shorter than its range
+    and a short workspace are all refused with AX_E_CAPACITY before anything
+    is enqueued (the output keeps its poison)."""
     x, arc = dna_archive
-    d, full = _decoder_with_index(arc)
+    d = _decoder_with_index(arc)
     rp = ax.RangePlan(d, max_blocks=2, max_tokens=1 << 16)
     work = torch.empty(rp.workspace_bytes, dtype=torch.uint8, device="cuda")
-    out = torch.empty(10 * B, dtype=torch.uint8, device="cuda")
+    out = torch.full((10 * B,), 0xCC, dtype=torch.uint8, device="cuda")
+    _say("capacity: closure")
     with pytest.raises(ax.AceapexError) as ei:
-        rp.decode([0], [10 * B], [out], full, work)
+        rp.decode([0], [10 * B], [out], work)
     assert ei.value.code == ax.AX_E_CAPACITY
+    rp2 = ax.RangePlan(d, max_blocks=512, max_tokens=1 << 18)
+    work2 = torch.empty(rp2.workspace_bytes, dtype=torch.uint8, device="cuda")
+    _say("capacity: short output")
+    with pytest.raises(ax.AceapexError) as ei:
+        rp2.decode([5 * B], [B], [out[: B - 1]], work2)
+    assert ei.value.code == ax.AX_E_CAPACITY
+    _say("capacity: short workspace")
+    with pytest.raises(ax.AceapexError) as ei:
+        rp2.decode([5 * B], [B], [out], work2[: rp2.workspace_bytes - 256])
+    assert ei.value.code == ax.AX_E_CAPACITY
+    need = d.range_workspace(5 * B, B)
+    with pytest.raises(ax.AceapexError) as ei:
+        d.decode_range(5 * B, B, out, torch.empty(need - 256, dtype=torch.uint8, device="cuda"))
+    assert ei.value.code == ax.AX_E_CAPACITY
+    with pytest.raises(ax.AceapexError) as ei:
+        d.decode_range(5 * B, B, out[: B - 1], torch.empty(need, dtype=torch.uint8, device="cuda"))
+    assert ei.value.code == ax.AX_E_CAPACITY
+    torch.cuda.synchronize()
+    assert (out.cpu().numpy() == 0xCC).all()
+
+
+def test_decode_range_with_its_own_workspace(dna_archive):
+    """aceapex_decode_range with exactly aceapex_range_workspace bytes, for
+    ranges from one byte to several blocks: every byte equals the input, and
+    the workspace is sized by the closure (far below the archive)."""
+    x, arc = dna_archive
+    d = _decoder_with_index(arc)
+    for off, ln in _ranges(x.size, 16, 13):
+        if ln > 40 * B:
+            continue
+        need = d.range_workspace(off, ln)
+        blocks, _, nb = d.closure_blocks([off], [ln])
+        assert need < (nb + 1) * B + 4 * d.info.n_blocks + nb * 140 * 1024 + (1 << 20)
+        work = torch.full((need,), 0xCC, dtype=torch.uint8, device="cuda")
+        out = torch.full((max(1, ln),), 0xCC, dtype=torch.uint8, device="cuda")
+        _say("decode_range", off, ln, need)
+        d.decode_range(off, ln, out, work)
+        assert np.array_equal(out[:ln].cpu().numpy(), x[off:off + ln]), (off, ln)
 
 
 def test_serving_results_same_alone_and_in_mix(dna_archive):
