@@ -136,15 +136,21 @@ def encode_forced(data, **kw):
 
 
 def assemble(data, cmds, **kw):
-    """Container from data + explicit command list [(kind, dst, len, src, rep)]."""
+    """Container from data + explicit commands: a list of (kind, dst, len, src,
+    rep) tuples, or an array of CMD_DTYPE records in output order."""
     a = _arr(data)
-    arr = (Cmd * max(1, len(cmds)))()
-    for i, (kind, dst, ln, src, rep) in enumerate(cmds):
-        arr[i].kind, arr[i].dst, arr[i].len, arr[i].src, arr[i].rep = kind, dst, ln, src, rep
+    if isinstance(cmds, np.ndarray):
+        arr = np.ascontiguousarray(cmds, dtype=CMD_DTYPE)
+        ptr, count = arr.ctypes.data_as(ctypes.POINTER(Cmd)), arr.size
+    else:
+        arr = (Cmd * max(1, len(cmds)))()
+        for i, (kind, dst, ln, src, rep) in enumerate(cmds):
+            arr[i].kind, arr[i].dst, arr[i].len, arr[i].src, arr[i].rep = kind, dst, ln, src, rep
+        ptr, count = arr, len(cmds)
     p = params(**kw)
     out = ctypes.POINTER(ctypes.c_uint8)()
     n = ctypes.c_uint64()
-    rc = lib().axo_assemble(_u8(a), a.size, arr, len(cmds), ctypes.byref(p), ctypes.byref(out), ctypes.byref(n))
+    rc = lib().axo_assemble(_u8(a), a.size, ptr, count, ctypes.byref(p), ctypes.byref(out), ctypes.byref(n))
     if rc:
         raise OracleError(rc, "assemble")
     return _take(out, n.value)
