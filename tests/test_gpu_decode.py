@@ -81,6 +81,25 @@ def test_no_rep_encoding():
     check("no_rep", x, arc)
 
 
+def test_full_size_no_rep_dna():
+    """The history-free encoding (no REP commands: every match carries its
+    offset) of the full-size DNA workload (253,952,000 B, seed 2), in the
+    benchmark's launch configuration."""
+    x = synth.dna(15500 * B, 2)
+    arc = ax.encode(x, threads=16, no_rep=1)
+    assert ax.read_info(arc).flags & 1
+    check("full-dna-no-rep", x, arc, modes=(ax.COPY_PERIODIC,))
+
+
+@pytest.mark.parametrize("window_log", [16, 22])
+def test_window_limited_encoder(window_log):
+    """Archives of the window-limited match finder (sources at most
+    2^window_log bytes back), the encoder setting the served workload uses."""
+    x = synth.dna(48 << 20, 9)
+    arc = ax.encode(x, threads=16, window_log=window_log)
+    check(f"window-log-{window_log}", x, arc, modes=(ax.COPY_PERIODIC,))
+
+
 @pytest.mark.parametrize("n", [0, 1, 17, 4095, 4096, 4097, B - 1, B, B + 1, 3 * B + 5])
 def test_edge_sizes(n):
     x = synth.dna(n, 40 + n)
