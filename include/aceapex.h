@@ -151,6 +151,23 @@ enum { AX_COPY_PERIODIC = 0, AX_COPY_SERIAL = 1 };
 int aceapex_decode_all(aceapex_decoder* dec, uint8_t* d_out, uint64_t out_cap, void* d_work, uint64_t work_len,
                        int copy_mode, void* stream);
 
+/* aceapex_decode_all without a caller workspace and without allocating: for
+ * callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * library-owned device array of AX_STATIC_SCRATCH_BYTES, one per device,
+ * held from the first call on that device until the process ends.  The call
+ * allocates nothing (no device or pinned memory, no events, streams or
+ * graphs): it never captures a graph and records no stage timing, whatever
+ * AX_OPT_GRAPH and aceapex_decoder_set_timing say.  All such calls on one
+ * device share the array, so calls that overlap on one device (two streams,
+ * two threads) race; calls ordered on one stream do not.  Read the device
+ * status with aceapex_decoder_status(dec, NULL, ...).
+ * Errors (before anything is enqueued): AX_E_CAPACITY when
+ * aceapex_decoder_workspace exceeds AX_STATIC_SCRATCH_BYTES or out_cap is
+ * below the decoded size; AX_E_ARG for null pointers. */
+#define AX_STATIC_SCRATCH_BYTES (128ull << 20)
+int aceapex_decode_all_static(aceapex_decoder* dec, uint8_t* d_out, uint64_t out_cap, int copy_mode, void* stream);
+
 /* Stage timing of the last decode on this handle (HIP events on `stream`,
  * recorded around the stages of every window and summed), in milliseconds:
  * entropy (rANS of the four streams), parse (commands, literal placement,
@@ -207,7 +224,8 @@ int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
 
 /* Read the device status word of a workspace after the work queued on
  * `stream`: synchronises `stream`.  *dev_err is 0 or an AX_E_* code;
- * *bad_block is the first failing block (or ~0). */
+ * *bad_block is the first failing block (or ~0).  d_work NULL: the static
+ * workspace of aceapex_decode_all_static on the current device. */
 int aceapex_decoder_status(aceapex_decoder* dec, void* d_work, void* stream, int32_t* dev_err,
                            uint64_t* bad_block);
 /* The same for any workspace (decode, batch or range). */

@@ -21,7 +21,8 @@ COPY_PERIODIC, COPY_SERIAL = 0, 1
 EXPORTS = [
     "aceapex_strerror", "aceapex_last_error", "aceapex_encode_params_default", "aceapex_encode_bound",
     "aceapex_encode", "aceapex_read_info", "aceapex_decoder_create", "aceapex_decoder_destroy",
-    "aceapex_decoder_info", "aceapex_decoder_workspace", "aceapex_decode_all", "aceapex_decoder_stage_ms",
+    "aceapex_decoder_info", "aceapex_decoder_workspace", "aceapex_decode_all", "aceapex_decode_all_static",
+    "aceapex_decoder_stage_ms",
     "aceapex_decoder_set_timing", "aceapex_decoder_status", "aceapex_decoder_set_option",
     "aceapex_workspace_status", "aceapex_batch_create", "aceapex_batch_destroy", "aceapex_batch_workspace",
     "aceapex_batch_set_option", "aceapex_batch_set_timing", "aceapex_batch_stage_ms", "aceapex_decode_batch",
@@ -32,6 +33,7 @@ EXPORTS = [
 OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH, OPT_ROUND0_TILE = 1, 2, 3, 4, 5, 6
 OPT_TAIL_MODE, OPT_JUMP_PASSES = 7, 8
 TAIL_JUMP, TAIL_CHASE = 0, 1
+STATIC_SCRATCH_BYTES = 128 << 20  # AX_STATIC_SCRATCH_BYTES
 
 
 class AceapexError(RuntimeError):
@@ -93,6 +95,7 @@ def _load():
     L.aceapex_decoder_info.argtypes = [vp, P(Info)]
     L.aceapex_decoder_workspace.argtypes = [vp, P(u64)]
     L.aceapex_decode_all.argtypes = [vp, vp, u64, vp, u64, ctypes.c_int, vp]
+    L.aceapex_decode_all_static.argtypes = [vp, vp, u64, ctypes.c_int, vp]
     L.aceapex_decoder_stage_ms.argtypes = [vp] + [P(ctypes.c_float)] * 4
     L.aceapex_decoder_set_timing.argtypes = [vp, ctypes.c_int]
     L.aceapex_decoder_status.argtypes = [vp, vp, vp, P(ctypes.c_int32), P(u64)]
@@ -237,6 +240,21 @@ class Decoder:
                                           _stream_ptr(stream)), "decode_all")
         return out[:n] if out.numel() != n else out
 
+    def decode_all_static(self, out, copy_mode=COPY_PERIODIC, stream=None):
+        """Enqueue a full decode whose workspace is the library's static
+        device scratch (aceapex_decode_all_static: allocates nothing)."""
+        _check(_load().aceapex_decode_all_static(self._h, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                                 int(copy_mode), _stream_ptr(stream)), "decode_all_static")
+        return out
+
+    def static_status(self, stream=None):
+        """Device status of the last aceapex_decode_all_static on the current device."""
+        err = ctypes.c_int32()
+        bad = ctypes.c_uint64()
+        _check(_load().aceapex_decoder_status(self._h, None, _stream_ptr(stream), ctypes.byref(err),
+                                              ctypes.byref(bad)), "decoder_status")
+        return err.value, bad.value
+
     def status(self, stream=None, work=None):
         err = ctypes.c_int32()
         bad = ctypes.c_uint64()
@@ -350,6 +368,21 @@ class Batch:
         _check(_load().aceapex_decode_batch(self._h, ctypes.c_void_p(w.data_ptr()), w.numel(), int(copy_mode),
                                             _stream_ptr(stream)), "decode_batch")
         return self._outs
+
+    def decode_all_static(self, out, copy_mode=COPY_PERIODIC, stream=None):
+        """Enqueue a full decode whose workspace is the library's static
+        device scratch (aceapex_decode_all_static: allocates nothing)."""
+        _check(_load().aceapex_decode_all_static(self._h, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                                 int(copy_mode), _stream_ptr(stream)), "decode_all_static")
+        return out
+
+    def static_status(self, stream=None):
+        """Device status of the last aceapex_decode_all_static on the current device."""
+        err = ctypes.c_int32()
+        bad = ctypes.c_uint64()
+        _check(_load().aceapex_decoder_status(self._h, None, _stream_ptr(stream), ctypes.byref(err),
+                                              ctypes.byref(bad)), "decoder_status")
+        return err.value, bad.value
 
     def status(self, stream=None, work=None):
         return workspace_status(self.workspace() if work is None else work, stream)

@@ -33,6 +33,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -2153,6 +2154,7 @@ struct Plan {
   hipGraph_t graph_def = nullptr;
   void* graph_work = nullptr;
   int graph_mode = -1;
+  bool graph_stale = false;  // rebuilt at the next decode that may allocate
   hipStream_t cap_stream = nullptr;
   ~Plan() {
     if (graph) (void)hipGraphExecDestroy(graph);
@@ -2347,6 +2349,19 @@ static int ensure_device(Plan* P) {
   if (!P->staged) {
     hipError_t e = hipEventCreateWithFlags(&P->staged, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "plan event");
+  }
+  // the jump-pass report of every window, so that a decode allocates nothing
+  if (P->wins.size() > P->jused_cap) {
+    if (P->jfeed_pending) (void)hipEventSynchronize(P->jfed), P->jfeed_pending = false;
+    if (P->h_jused) (void)hipHostFree(P->h_jused), P->h_jused = nullptr;
+    P->jused_cap = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&P->h_jused), 4 * P->wins.size());
+    if (e != hipSuccess) return hip_fail(e, "pass report staging");
+    P->jused_cap = P->wins.size();
+  }
+  if (!P->jfed) {
+    hipError_t e = hipEventCreateWithFlags(&P->jfed, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "pass report event");
   }
   return AX_OK;
 }
@@ -2704,7 +2719,10 @@ static void enqueue(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool time
   else enqueue_out<OutDirect>(P, w, copy_mode, s, timed, feedback);
 }
 
-int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s) {
+// A decode: checks, then the launch sequence on s.  no_alloc: no graph and no
+// stage timing (both may create runtime objects); everything else a decode
+// uses was allocated with the plan.
+static int run_plan(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s, bool no_alloc) {
   if (!d_work) return fail(AX_E_ARG, "null workspace");
   if (work_len < P->lay.total) return fail(AX_E_CAPACITY, "workspace too small");
   if (reinterpret_cast<uintptr_t>(d_work) & 255) return fail(AX_E_ARG, "workspace must be 256-byte aligned");
@@ -2736,24 +2754,13 @@ int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_
       else all = false;
     }
     P->jsettled = all;
-    if (P->graph) (void)hipGraphExecDestroy(P->graph), P->graph = nullptr;  // pass counts changed
+    P->graph_stale = P->graph != nullptr;  // pass counts changed
   }
+  if (P->graph_stale && !no_alloc) (void)hipGraphExecDestroy(P->graph), P->graph = nullptr, P->graph_stale = false;
   const bool feedback = P->learn && !P->jsettled && !P->jfeed_pending && P->opt.tail_mode == 0 && !P->opt.jump_passes &&
-                        copy_mode != AX_COPY_SERIAL && !P->wins.empty();
-  if (feedback) {
-    if (P->wins.size() > P->jused_cap) {
-      if (P->h_jused) (void)hipHostFree(P->h_jused), P->h_jused = nullptr;
-      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&P->h_jused), 4 * P->wins.size());
-      if (e != hipSuccess) return hip_fail(e, "pass report staging");
-      P->jused_cap = P->wins.size();
-    }
-    if (!P->jfed) {
-      hipError_t e = hipEventCreateWithFlags(&P->jfed, hipEventDisableTiming);
-      if (e != hipSuccess) return hip_fail(e, "pass report event");
-    }
-    std::fill(P->h_jused, P->h_jused + P->wins.size(), 0u);
-  }
-  if (P->opt.graph && !timed) {
+                        copy_mode != AX_COPY_SERIAL && !P->wins.empty() && P->jused_cap >= P->wins.size() && P->jfed;
+  if (feedback) std::fill(P->h_jused, P->h_jused + P->wins.size(), 0u);
+  if (P->opt.graph && !timed && !no_alloc) {
     // the launch sequence of every window and round, captured once and replayed
     if (!P->graph || P->graph_work != d_work || P->graph_mode != copy_mode) {
       if (P->graph) (void)hipGraphExecDestroy(P->graph), P->graph = nullptr;
@@ -2775,12 +2782,13 @@ int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_
     if (e != hipSuccess) return hip_fail(e, "graph launch");
     return AX_OK;
   }
-  if (timed) {
+  const bool timed_now = timed && !no_alloc;
+  if (timed_now) {
     int rc = ensure_events(P);
     if (rc) return rc;
   }
-  enqueue(P, w, copy_mode, s, timed, feedback);
-  if (timed) P->timed_windows = P->wins.size();
+  enqueue(P, w, copy_mode, s, timed_now, feedback);
+  if (timed_now) P->timed_windows = P->wins.size();
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   if (feedback) {
@@ -2789,6 +2797,13 @@ int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_
     P->jfeed_pending = true;
   }
   return AX_OK;
+}
+
+int plan_run(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s) {
+  return run_plan(P, d_work, work_len, copy_mode, s, false);
+}
+int plan_run_no_alloc(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s) {
+  return run_plan(P, d_work, work_len, copy_mode, s, true);
 }
 
 int workspace_status(void* d_work, hipStream_t s, int32_t* dev_err, uint64_t* bad_block) {
@@ -2802,6 +2817,42 @@ int workspace_status(void* d_work, hipStream_t s, int32_t* dev_err, uint64_t* ba
 }
 
 }  // namespace ax
+
+// ------------------------------------------------- allocation-free decode --
+//
+// Workspace of aceapex_decode_all_static: a library-owned device array, so
+// that callers that cannot allocate device memory can still decode.  Every
+// device the library runs on holds its own copy (at its own address, looked
+// up once per device with that device current) until the process ends.  All
+// such decodes on one device share it: calls that overlap on one device race.
+// The launch sequence initialises every part of a workspace it reads, so the
+// contents a previous call left do not matter.
+static __device__ __align__(256) uint8_t scratch[AX_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr uint64_t kStaticScratchBytes = AX_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kMaxDevices] = {};
+
+// Device address of the static scratch on the current device.
+int static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return ax::fail(AX_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return ax::fail(AX_E_HIP, hipGetErrorString(e));
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 255)) return ax::fail(AX_E_HIP, "static scratch address");
+    g_scratch_at[dev] = p;
+  }
+  *out = g_scratch_at[dev];
+  return AX_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -2916,8 +2967,24 @@ int aceapex_decode_all(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, voi
   return ax::plan_run(d->plan, d_work, work_len, copy_mode, reinterpret_cast<hipStream_t>(stream));
 }
 
+int aceapex_decode_all_static(aceapex_decoder* d, uint8_t* d_out, uint64_t out_cap, int copy_mode, void* stream) {
+  if (!d || (!d_out && d->info.n_bytes)) return ax::fail(AX_E_ARG, "null argument");
+  if (out_cap < d->info.n_bytes) return ax::fail(AX_E_CAPACITY, "output smaller than the decoded size");
+  if (ax::plan_workspace(d->plan) > kStaticScratchBytes)
+    return ax::fail(AX_E_CAPACITY, "the archive needs more workspace than the static scratch holds");
+  void* w = nullptr;
+  int rc = static_scratch(&w);
+  if (rc) return rc;
+  ax::plan_set_out(d->plan, 0, d_out);
+  return ax::plan_run_no_alloc(d->plan, w, kStaticScratchBytes, copy_mode, reinterpret_cast<hipStream_t>(stream));
+}
+
 int aceapex_decoder_status(aceapex_decoder* d, void* d_work, void* stream, int32_t* dev_err, uint64_t* bad_block) {
-  if (!d || !d_work || !dev_err || !bad_block) return ax::fail(AX_E_ARG, "null argument");
+  if (!d || !dev_err || !bad_block) return ax::fail(AX_E_ARG, "null argument");
+  if (!d_work) {  // the static scratch of aceapex_decode_all_static on the current device
+    int rc = static_scratch(&d_work);
+    if (rc) return rc;
+  }
   return ax::workspace_status(d_work, reinterpret_cast<hipStream_t>(stream), dev_err, bad_block);
 }
 

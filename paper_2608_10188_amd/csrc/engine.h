@@ -69,6 +69,8 @@ int plan_get_option(const Plan* p, int option, int64_t* value);
 int plan_set_timing(Plan* p, int enable);
 int plan_stage_ms(Plan* p, float* ans, float* parse, float* copy, float* remainder);
 int plan_run(Plan* p, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s);
+// the same, creating nothing: no graph, no stage timing
+int plan_run_no_alloc(Plan* p, void* d_work, uint64_t work_len, int copy_mode, hipStream_t s);
 int workspace_status(void* d_work, hipStream_t s, int32_t* dev_err, uint64_t* bad_block);
 
 }  // namespace ax
