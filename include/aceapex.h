@@ -222,6 +222,17 @@ enum { AX_OPT_TAIL_MODE = 7 };
 enum { AX_OPT_JUMP_PASSES = 8 };
 int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
 
+/* The entropy stage alone (Setup: per-block rANS of the LIT, LEN, OFF and
+ * CMD streams) for archive blocks [first, first + count), count at most
+ * 131072: their decoded streams copied to h_out (cap bytes), packed block
+ * after block in the order LIT, LEN, OFF, CMD; n_syms (4 * count entries)
+ * receives each stream's length in that order.  For checking the entropy
+ * stage on its own.  d_work: the decode_all workspace.  Synchronous on
+ * `stream`.  Errors: AX_E_RANGE (blocks), AX_E_CAPACITY (workspace or
+ * h_out too small), the device status code of a corrupt stream. */
+int aceapex_decoder_streams(aceapex_decoder* dec, uint64_t first, uint64_t count, void* d_work, uint64_t work_len,
+                            void* stream, uint8_t* h_out, uint64_t cap, uint32_t* n_syms);
+
 /* Read the device status word of a workspace after the work queued on
  * `stream`: synchronises `stream`.  *dev_err is 0 or an AX_E_* code;
  * *bad_block is the first failing block (or ~0).  d_work NULL: the static
@@ -265,6 +276,16 @@ int aceapex_decode_batch(aceapex_batch* batch, void* d_work, uint64_t work_len, 
  * closure computable without decoding the archive).  d_work: the
  * decode_all workspace.  Synchronous; host memory 16 bytes per match. */
 int aceapex_decoder_build_index(aceapex_decoder* dec, void* d_work, uint64_t work_len, void* stream);
+
+/* The device parse's matches, from the token index (build it first):
+ * matches [first, first + count) in archive order (block b's matches are
+ * the index's entries from the cumulative match count of block b, in
+ * output order), each its source, destination and length (Setup: absolute
+ * source offsets; REP commands appear with the source their distance
+ * history resolved to).  For checking the parse stage on its own.  Errors:
+ * AX_E_ARG (index not built), AX_E_RANGE. */
+int aceapex_decoder_tokens(const aceapex_decoder* dec, uint64_t first, uint64_t count, uint64_t* src, uint64_t* dst,
+                           uint32_t* len);
 
 /* Byte-precise source closure of n ranges: the ascending union of the blocks
  * holding any byte the ranges need (their own bytes and, transitively, the

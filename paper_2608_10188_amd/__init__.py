@@ -28,7 +28,7 @@ EXPORTS = [
     "aceapex_batch_set_option", "aceapex_batch_set_timing", "aceapex_batch_stage_ms", "aceapex_decode_batch",
     "aceapex_decoder_build_index", "aceapex_closure_blocks", "aceapex_range_plan_create", "aceapex_range_plan_destroy",
     "aceapex_range_plan_workspace", "aceapex_range_plan_last", "aceapex_decode_ranges", "aceapex_decode_range",
-    "aceapex_range_workspace",
+    "aceapex_range_workspace", "aceapex_decoder_streams", "aceapex_decoder_tokens",
 ]
 OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH, OPT_ROUND0_TILE = 1, 2, 3, 4, 5, 6
 OPT_TAIL_MODE, OPT_JUMP_PASSES = 7, 8
@@ -120,6 +120,8 @@ def _load():
     L.aceapex_decode_ranges.argtypes = [vp, ctypes.c_uint32, u64p, u64p, P(vp), u64p, vp, u64, ctypes.c_int, vp]
     L.aceapex_decode_range.argtypes = [vp, u64, u64, vp, u64, vp, u64, vp]
     L.aceapex_range_workspace.argtypes = [vp, u64, u64, u64p]
+    L.aceapex_decoder_streams.argtypes = [vp, u64, u64, vp, u64, vp, u8p, u64, P(ctypes.c_uint32)]
+    L.aceapex_decoder_tokens.argtypes = [vp, u64, u64, u64p, u64p, P(ctypes.c_uint32)]
     _lib = L
     return L
 
@@ -283,6 +285,40 @@ class Decoder:
                                             out.numel(), ctypes.c_void_p(work.data_ptr()), work.numel(),
                                             _stream_ptr(stream)), "decode_range")
         return out
+
+    def streams(self, first, count=1, stream=None, work=None):
+        """The entropy stage alone: the decoded LIT, LEN, OFF and CMD streams
+        of blocks [first, first + count), one dict per block (synchronous)."""
+        w = self.workspace() if work is None else work
+        B, mm = int(self.info.block_size), int(self.info.min_match)
+        cap = int(count) * (5 * B + 10 * (B // mm + 1) + 16)
+        buf = np.zeros(max(1, cap), np.uint8)
+        n = np.zeros(max(1, 4 * int(count)), np.uint32)
+        _check(_load().aceapex_decoder_streams(self._h, int(first), int(count), ctypes.c_void_p(w.data_ptr()),
+                                               w.numel(), _stream_ptr(stream), _u8(buf), cap,
+                                               n.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))), "decoder_streams")
+        out, at = [], 0
+        for i in range(int(count)):
+            blk = {}
+            for k, name in enumerate(("lit", "len", "off", "cmd")):
+                m = int(n[4 * i + k])
+                blk[name] = buf[at: at + m].copy()
+                at += m
+            out.append(blk)
+        return out
+
+    def tokens(self, first, count):
+        """Matches [first, first + count) of the device parse (build_index
+        first): (src, dst, len) arrays."""
+        src = np.zeros(max(1, int(count)), np.uint64)
+        dst = np.zeros(max(1, int(count)), np.uint64)
+        ln = np.zeros(max(1, int(count)), np.uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        _check(_load().aceapex_decoder_tokens(self._h, int(first), int(count), src.ctypes.data_as(u64p),
+                                              dst.ctypes.data_as(u64p),
+                                              ln.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))), "decoder_tokens")
+        c = int(count)
+        return src[:c], dst[:c], ln[:c]
 
     def closure_blocks(self, offs, lens, threads=0, want_blocks=True):
         """Union source closure of ranges: (ascending block array, match count)."""

@@ -2500,6 +2500,55 @@ int plan_parse_tokens(Plan* P, void* d_work, uint64_t work_len, hipStream_t s, u
   }
   return AX_OK;
 }
+int block_streams(const aceapex_decoder* d, uint64_t first, uint64_t count, void* d_work, uint64_t work_len,
+                  hipStream_t s, uint8_t* h_out, uint64_t cap, uint32_t* n_syms) {
+  if (count == 0) return AX_OK;
+  if (first >= d->info.n_blocks || count > d->info.n_blocks - first || count > kWindowBlocks)
+    return fail(AX_E_RANGE, "blocks outside the archive or beyond one window");
+  std::vector<uint64_t> bl(count);
+  for (uint64_t i = 0; i < count; ++i) bl[i] = first + i;
+  Plan* P = nullptr;
+  int rc = plan_create({JobSpec{d, nullptr, std::move(bl)}}, &P);
+  if (rc) return rc;
+  struct Guard {
+    Plan* p;
+    ~Guard() { delete p; }
+  } guard{P};
+  if (work_len < P->lay.total) return fail(AX_E_CAPACITY, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(d_work) & 255) return fail(AX_E_ARG, "workspace must be 256-byte aligned");
+  uint8_t* w = static_cast<uint8_t*>(d_work);
+  const Layout& L = P->lay;
+  DevStatus* st = reinterpret_cast<DevStatus*>(w + L.status);
+  const Plan::Win& W = P->wins.front();
+  hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st, 1);
+  AnsArgs aa{P->d_jobs, P->d_wbl, W.items, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
+             P->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
+  hipLaunchKernelGGL(k_ans, dim3(4 * W.items), dim3(64), 0, s, aa);
+  hipError_t e = hipMemcpyAsync(n_syms, w + L.nsym, 16 * count, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "stream counts");
+  int32_t err = 0;
+  uint64_t bad = 0;
+  rc = workspace_status(d_work, s, &err, &bad);
+  if (rc) return rc;
+  if (err) return fail(err, "device status of the entropy stage");
+  // packed: per block LIT, LEN, OFF, CMD (the slot order of the counts)
+  const uint64_t at[4] = {L.lit, L.len, L.off, L.cmd};
+  const uint64_t stride[4] = {P->slot_b, P->len_cap, P->off_cap, P->slot_b};
+  uint64_t need = 0;
+  for (uint64_t i = 0; i < 4 * count; ++i) need += n_syms[i];
+  if (need > cap) return fail(AX_E_CAPACITY, "host buffer smaller than the streams");
+  uint64_t o = 0;
+  for (uint64_t i = 0; i < count && e == hipSuccess; ++i)
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+      const uint32_t n = n_syms[4 * i + k];
+      if (n) e = hipMemcpyAsync(h_out + o, w + at[k] + i * stride[k], n, hipMemcpyDeviceToHost, s);
+      o += n;
+    }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? AX_OK : hip_fail(e, "stream copy");
+}
+
 void plan_destroy(Plan* P) { delete P; }
 uint64_t plan_workspace(const Plan* P) { return P->lay.total; }
 uint64_t plan_tokens(const Plan* P) { return P->n_tokens; }
@@ -2977,6 +3026,13 @@ int aceapex_decode_all_static(aceapex_decoder* d, uint8_t* d_out, uint64_t out_c
   if (rc) return rc;
   ax::plan_set_out(d->plan, 0, d_out);
   return ax::plan_run_no_alloc(d->plan, w, kStaticScratchBytes, copy_mode, reinterpret_cast<hipStream_t>(stream));
+}
+
+int aceapex_decoder_streams(aceapex_decoder* d, uint64_t first, uint64_t count, void* d_work, uint64_t work_len,
+                            void* stream, uint8_t* h_out, uint64_t cap, uint32_t* n_syms) {
+  if (!d || (count && (!d_work || !n_syms || (!h_out && cap)))) return ax::fail(AX_E_ARG, "null argument");
+  return ax::block_streams(d, first, count, d_work, work_len, reinterpret_cast<hipStream_t>(stream), h_out, cap,
+                           n_syms);
 }
 
 int aceapex_decoder_status(aceapex_decoder* d, void* d_work, void* stream, int32_t* dev_err, uint64_t* bad_block) {

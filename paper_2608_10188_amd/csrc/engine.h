@@ -59,6 +59,11 @@ void plan_set_learn(Plan* p, bool learn);
 // tokens (src; dst | (len-1) << 48) are copied to host arrays in archive
 // order.  Synchronous.
 int plan_parse_tokens(Plan* p, void* d_work, uint64_t work_len, hipStream_t s, uint64_t* src, uint64_t* dstlen);
+// The entropy stage alone for archive blocks [first, first + count) (one
+// window): their four decoded streams copied to h_out packed block after
+// block (LIT, LEN, OFF, CMD), n_syms[4 i + k] their lengths.  Synchronous.
+int block_streams(const aceapex_decoder* d, uint64_t first, uint64_t count, void* d_work, uint64_t work_len,
+                  hipStream_t s, uint8_t* h_out, uint64_t cap, uint32_t* n_syms);
 void plan_destroy(Plan* p);
 uint64_t plan_workspace(const Plan* p);
 uint64_t plan_tokens(const Plan* p);

@@ -355,6 +355,21 @@ int aceapex_decoder_build_index(aceapex_decoder* d, void* d_work, uint64_t work_
   return ax::plan_parse_tokens(d->plan, d_work, work_len, s, d->idx_src.data(), d->idx_dstlen.data());
 }
 
+int aceapex_decoder_tokens(const aceapex_decoder* d, uint64_t first, uint64_t count, uint64_t* src, uint64_t* dst,
+                           uint32_t* len) {
+  if (!d || (count && (!src || !dst || !len))) return ax::fail(AX_E_ARG, "null argument");
+  if (d->idx_dstlen.size() != d->info.n_matches) return ax::fail(AX_E_ARG, "token index not built");
+  if (first > d->info.n_matches || count > d->info.n_matches - first)
+    return ax::fail(AX_E_RANGE, "matches outside the archive");
+  for (uint64_t i = 0; i < count; ++i) {
+    const uint64_t w = d->idx_dstlen[first + i];
+    src[i] = d->idx_src[first + i];
+    dst[i] = w & ((1ull << 48) - 1);
+    len[i] = uint32_t(w >> 48) + 1;
+  }
+  return AX_OK;
+}
+
 int aceapex_closure_blocks(aceapex_decoder* d, uint32_t n, const uint64_t* offs, const uint64_t* lens,
                            uint64_t* blocks, uint64_t cap, uint64_t* n_blocks, uint64_t* n_tokens, uint32_t threads) {
   if (!d || (n && (!offs || !lens)) || !n_blocks) return ax::fail(AX_E_ARG, "null argument");
