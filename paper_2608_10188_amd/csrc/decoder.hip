@@ -410,6 +410,7 @@ struct ParseArgs {
   uint8_t* done;             // per token: kPending until the match layer copies it
   DevStatus* st;
   int write_out;             // 0: tokens only (the token-index build), no output bytes
+  uint16_t* mcov;            // match coverage: per window position, set when a match writes it (16 per u16)
 };
 
 // History maps.  A command acts on the four-entry distance history as a map
@@ -455,6 +456,9 @@ struct ParseShared {
   uint32_t wterm[4];
   int32_t wlast[4];
   uint32_t leb_found, leb_cursor;
+  // coverage bits of the 16-byte group a chunk leaves open, by chunk parity
+  // (a chunk reads its predecessor's while it may write its own)
+  uint32_t mcarry[2];
   int bad;
   alignas(4) uint8_t anyb[2][4];  // block_any: one byte per wave, two call sites
 };
@@ -622,7 +626,7 @@ __device__ bool leb_values(Src src, uint32_t n, uint32_t* cursor, uint32_t count
 }
 
 // Six waves per SIMD (at most 80 VGPRs), as many as the LDS allows.
-template <class O>
+template <class O, bool kCovMap>
 __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
   __shared__ ParseShared sh;
   const uint32_t item = blockIdx.x, t = threadIdx.x;
@@ -783,6 +787,7 @@ __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
       int32_t r = int32_t(sh.runpre[w] + __popcll(sh.runbits[w] & (~0ull >> (63 - (d0 & 63))))) - 1;
       if (r < 0 || d0 >= sh.runend[r]) ++r;  // the run holding d0, else the next one
       u32x4 val = {0, 0, 0, 0}, msk = {0, 0, 0, 0};
+      uint32_t lit16 = 0;  // the group's literal bytes in this chunk
       for (; r < int32_t(n_runs) && sh.runbeg[r] < d1; ++r) {
         const uint32_t x0 = max(d0, uint32_t(sh.runbeg[r])), x1 = min(d1, uint32_t(sh.runend[r]));
         const int32_t l0 = int32_t(16 * c) - int32_t(sh.rundelta[r]);  // literal index of the group's byte 0
@@ -800,7 +805,15 @@ __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
                           __builtin_amdgcn_perm(0u, 0u, sel.z), __builtin_amdgcn_perm(0u, 0u, sel.w)};
         val = (val & ~bm) | (e & bm);
         msk |= bm;
+        lit16 |= m16;
         if (sh.runend[r] >= d1) break;
+      }
+      if (kCovMap) {  // match coverage of the group: its bytes in this chunk that no literal fills
+        uint32_t m = ((1u << (d1 - 16 * c)) - 1u) & ~((1u << (d0 - 16 * c)) - 1u) & ~lit16;
+        const uint32_t par = (c0 / kParseThreads) & 1;
+        if (d0 > 16 * c) m |= sh.mcarry[par ^ 1];  // the group began in the previous chunk
+        if (d1 < 16 * c + 16 && d1 < blen) sh.mcarry[par] = m;  // it goes on in the next chunk
+        else a.mcov[uint64_t(item) * (a.slot_b / 16) + c] = uint16_t(m);
       }
       if (msk.x | msk.y | msk.z | msk.w) {
         u32x4& cell = *reinterpret_cast<u32x4*>(sh.tile + 16 * c);
@@ -858,6 +871,8 @@ struct CopyArgs {
   uint32_t* J;                // pointer jumping: one entry per window position
   uint64_t* lmap;             // pointer jumping: leftover map
   uint32_t S;                 // position stride of a window block
+  const uint64_t* mcov;       // match coverage of the window positions (the parse writes it when round 0
+                              // is the only bulk round; null: round 0 finds every cover)
 };
 
 __device__ inline void token_at(const uint64_t* tok, uint64_t t, uint64_t& src, uint64_t& dst, uint32_t& len) {
@@ -901,6 +916,21 @@ __device__ inline void find_cover(const CopyArgs& a, const WinBlock& wb, uint32_
   lo = p;
   cnt = 0;
   while (p + cnt < end_tok && (a.tok[2 * uint64_t(p + cnt) + 1] & ((1ull << 48) - 1)) < s1) ++cnt;
+}
+
+// Round 0 leaves the cover of its pending tokens to the round that first
+// needs it (the covers of its ready tokens are never needed).
+constexpr uint32_t kCovLazy = 0xFFFFFFFFu;
+__device__ inline void cover_of(const CopyArgs& a, uint32_t t, uint64_t src, uint64_t dst, uint32_t len,
+                                uint32_t& lo, uint32_t& cnt) {
+  lo = a.cov[2 * t];
+  cnt = a.cov[2 * t + 1];
+  if (cnt != kCovLazy) return;
+  const WinBlock wb = a.wbl[a.tblk[t]];
+  const uint64_t dist = dst - src;
+  find_cover(a, wb, a.jobs[wb.job].B, src, src + (dist < len ? dist : len), lo, cnt);
+  a.cov[2 * t] = lo;
+  a.cov[2 * t + 1] = cnt;
 }
 
 // The output of token t's archive.
@@ -1117,6 +1147,31 @@ __device__ inline bool window_block(const WinBlock* wbl, uint32_t S, const WinBl
   return true;
 }
 
+// Whether no match of this window writes a byte of [s0, s1) of the job of
+// window block wb (block `item`, whose bytes start at archive position bs):
+// those bytes are literals or final, so a token reading them is ready in
+// round 0.  Read from the match coverage the parse wrote; bytes of blocks
+// outside the window are final or not needed (as for find_cover).
+__device__ inline bool sources_literal(const CopyArgs& a, const WinBlock& wb, uint32_t item, uint64_t bs, uint32_t B,
+                                       uint64_t s0, uint64_t s1) {
+  const uint32_t lb = __builtin_ctz(B);
+  const AX_GLOBAL uint64_t* const mc = gp(a.mcov);
+  while (s0 < s1) {
+    const uint64_t qb = s0 >> lb, e = min(s1, (qb + 1) << lb);
+    uint32_t wq = item * a.S;
+    if (qb == (bs >> lb) || window_block(a.wbl, a.S, wb, qb, wq)) {
+      const uint32_t p0 = wq + uint32_t(s0 & (B - 1)), p1 = p0 + uint32_t(e - s0);  // window positions
+      for (uint32_t w = p0 >> 6; w <= (p1 - 1) >> 6; ++w) {
+        const uint32_t lo = w == (p0 >> 6) ? (p0 & 63) : 0, hi = w == ((p1 - 1) >> 6) ? ((p1 - 1) & 63) : 63;
+        const uint64_t m = (~0ull >> (63 - hi)) & (~0ull << lo);
+        if (mc[w] & m) return false;
+      }
+    }
+    s0 = e;
+  }
+  return true;
+}
+
 // Mark this wave's pending tokens (one per lane: `pend`, token t).  `row`:
 // when not null, every token lies in window block `row_item` and its bits go
 // to that block's LDS row (32-bit words); else to the leftover map with
@@ -1230,7 +1285,7 @@ __device__ void mark_wave(const CopyArgs& a, bool pend, uint32_t t, MarkStage& m
 // read nor written.  Tokens of at least kSplitToken bytes go to k_long.
 // Leftovers go to sublist (t / 64) mod kSub, so a sublist holds at most
 // ceil(T / 64 / kSub) * 64 tokens.
-template <class O>
+template <class O, bool kCovMap>
 __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t tile[kMaxB];
   __shared__ uint32_t dirty[kMaxB / 16 / 32];  // chunks of the tile that receive match bytes
@@ -1257,15 +1312,22 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
     const uint32_t t = base + threadIdx.x;
     const bool act = t < t1;
     uint64_t src = 0, dst = 0;
-    uint32_t len = 0, lo = 0, cnt = 0;
+    uint32_t len = 0;
+    bool ready = false;
     if (act) {
       token_at(a.tok, t, src, dst, len);
-      const uint64_t dist = dst - src;
-      find_cover(a, wb, B, src, src + (dist < len ? dist : len), lo, cnt);
-      a.cov[2 * t] = lo;
-      a.cov[2 * t + 1] = cnt;
+      const uint64_t dist = dst - src, s1 = src + (dist < len ? dist : len);
+      if (kCovMap) {  // the only round: readiness from the coverage map, covers when first needed
+        ready = sources_literal(a, wb, item, bs, B, src, s1);
+        if (!ready) a.cov[2 * t + 1] = kCovLazy;
+      } else {
+        uint32_t lo, cnt;
+        find_cover(a, wb, B, src, s1, lo, cnt);
+        a.cov[2 * t] = lo;
+        a.cov[2 * t + 1] = cnt;
+        ready = cnt == 0;
+      }
     }
-    const bool ready = act && cnt == 0;
     const bool split = ready && !a.serial && len >= kSplitToken;
     const uint64_t sm = __ballot(split);
     if (sm) {
@@ -1497,8 +1559,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     if (act) {
       token_at(a.tok, t, src, dst, len);
       out = token_out<O>(a, t);
-      lo = a.cov[2 * t];
-      cnt = a.cov[2 * t + 1];
+      cover_of(a, t, src, dst, len, lo, cnt);
     }
     bool ready = act;
     for (uint32_t i = 0; i < cnt && ready; ++i) ready = a.done[lo + i] < a.round;
@@ -1646,8 +1707,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_tail(CopyArgs a) {
       if (pending) {
         token_at(a.tok, t, src, dst, len);
         out = token_out<O>(a, t);
-        lo = a.cov[2 * t];
-        cnt = a.cov[2 * t + 1];
+        cover_of(a, t, src, dst, len, lo, cnt);
       }
       uint64_t spins = 0;
       while (__ballot(pending)) {
@@ -1722,8 +1782,7 @@ struct JumpArgs {
   const uint32_t* llist;  // long pending tokens: kSub sublists of sub_cap
   const uint32_t* lcnt;   // their counters, kCounterStride apart
   uint32_t sub_cap;
-  uint32_t* wlist;     // leftover-map words with bits set, ascending
-  uint32_t* wpsum;     // per list-build workgroup: its words with bits set
+  uint32_t* wlist;     // leftover-map words with bits set
   DevStatus* st;
   uint32_t pass;
 };
@@ -1787,11 +1846,11 @@ __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
     const JobDev jd = a.jobs[wb.job];
     const uint32_t lb = __builtin_ctz(jd.B);
     const uint64_t bs = wb.b << lb, dist = dst - src;
+    uint64_t cb = ~0ull;  // the source block last looked up, kept over the lane's passes
+    uint32_t cbase = 0;
+    bool cin = false;
     for (uint32_t k0 = lane * kJMarkBytes; k0 < len; k0 += 64 * kJMarkBytes) {
       uint64_t j = dist > k0 ? k0 : uint64_t(k0 % uint32_t(dist));
-      uint64_t cb = ~0ull;
-      uint32_t cbase = 0;
-      bool cin = false;
       uint32_t mw = ~0u, mbits = 0;
       for (uint32_t k = k0; k < k0 + kJMarkBytes && k < len; ++k) {
         const uint64_t sp = src + j, sb = sp >> lb;
@@ -1811,39 +1870,21 @@ __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
   }
 }
 
-constexpr uint32_t kJDense = 0xFFFFFFFFu;  // n_jwords: the map is walked whole (dense)
-
-// The work list: the leftover-map words with bits set, ascending (two
-// launches: counts per workgroup of kJListWords words, then the scatter).
+// The work list: the leftover-map words with bits set, in one pass (each
+// workgroup takes kJListWords words, finds its busy ones and appends them at
+// a place reserved with one atomic add: ascending within a workgroup, in any
+// order across them).  When more than a quarter of the map's words are busy
+// the kernels below walk the whole map instead (dense).
 constexpr uint32_t kJListWords = 16 * kCopyThreads;
-__global__ __launch_bounds__(kCopyThreads) void k_jlcount(JumpArgs a) {
-  __shared__ uint32_t red[kCopyThreads / 64];
-  if (jump_failed(a.st)) return;
-  const uint64_t words = uint64_t(a.n_items) * (a.S / 64), w0 = uint64_t(blockIdx.x) * kJListWords;
-  uint32_t c = 0;
-  for (uint32_t k = threadIdx.x; k < kJListWords; k += kCopyThreads)
-    if (w0 + k < words) c += a.lmap[w0 + k] != 0;
-  c = block_sum_u32(c, red);
-  if (threadIdx.x == 0) a.wpsum[blockIdx.x] = c;
+__device__ inline bool jump_dense(const JumpArgs& a, uint32_t n_words) {
+  return uint64_t(n_words) * 4 > uint64_t(a.n_items) * (a.S / 64);
 }
 
 __global__ __launch_bounds__(kCopyThreads) void k_jlist(JumpArgs a) {
-  __shared__ uint32_t red[kCopyThreads / 64];
   __shared__ uint32_t wtot[kCopyThreads / 64];
+  __shared__ uint32_t base;
   if (jump_failed(a.st)) return;
   const uint64_t words = uint64_t(a.n_items) * (a.S / 64), w0 = uint64_t(blockIdx.x) * kJListWords;
-  uint32_t before = 0, all = 0;
-  for (uint32_t g = threadIdx.x; g < gridDim.x; g += kCopyThreads) {
-    const uint32_t c = a.wpsum[g];
-    if (g < blockIdx.x) before += c;
-    all += c;
-  }
-  const uint32_t base = block_sum_u32(before, red);
-  const uint32_t busy = block_sum_u32(all, red);
-  if (uint64_t(busy) * 4 > words) {  // dense: the kernels walk the whole map
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->n_jwords = kJDense;
-    return;
-  }
   constexpr uint32_t kPer = kJListWords / kCopyThreads;  // consecutive words per thread
   uint32_t bits = 0, c = 0;
 #pragma unroll
@@ -1855,6 +1896,12 @@ __global__ __launch_bounds__(kCopyThreads) void k_jlist(JumpArgs a) {
   const uint32_t ex = wave_excl_sum(c, &tot);
   if (lane_id() == 0) wtot[threadIdx.x >> 6] = tot;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t all = 0;
+    for (uint32_t k = 0; k < kCopyThreads / 64; ++k) all += wtot[k];
+    base = all ? atomicAdd(&a.st->n_jwords, all) : 0u;
+  }
+  __syncthreads();
   uint32_t at = base + ex;
   for (uint32_t k = 0; k < (threadIdx.x >> 6); ++k) at += wtot[k];
   while (bits) {
@@ -1862,7 +1909,6 @@ __global__ __launch_bounds__(kCopyThreads) void k_jlist(JumpArgs a) {
     bits &= bits - 1;
     a.wlist[at++] = uint32_t(w0 + kPer * threadIdx.x + q);
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kCopyThreads - 1) a.st->n_jwords = at;
 }
 
 // The position-driven kernels below visit the leftover-map words with bits
@@ -1898,7 +1944,7 @@ __device__ inline void walk_words(const JumpArgs& a, const uint64_t* map, F&& f)
   const uint64_t wave = uint64_t(blockIdx.x) * (kCopyThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t n = a.st->n_jwords;
   WordGroup w;
-  if (n == kJDense) {
+  if (jump_dense(a, n)) {
     const uint64_t words = uint64_t(a.n_items) * (a.S / 64);
     const uint64_t steps = (words + kJChunk * 4 * waves - 1) / (kJChunk * 4 * waves);
     for (uint64_t i = 0; i < steps; ++i) {
@@ -1972,7 +2018,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_jinit(JumpArgs a) {
     }
   });
   // the dense walk visits only busy words: the others' active bits are zero
-  if (a.st->n_jwords == kJDense) {
+  if (jump_dense(a, a.st->n_jwords)) {
     const uint64_t words = uint64_t(a.n_items) * (a.S / 64);
     for (uint64_t w = uint64_t(blockIdx.x) * kCopyThreads + threadIdx.x; w < words;
          w += uint64_t(gridDim.x) * kCopyThreads)
@@ -2103,7 +2149,7 @@ namespace ax {
 
 struct Layout {
   uint64_t status, nsym, lit, cmd, off, len, tok, tblk, cov, done, counts, jflags, list0, list1, llist, pbits, pcnt,
-      plist, lmap, amap, ibase, wlist, wpsum, total;
+      plist, lmap, mcov, amap, ibase, wlist, total;
   uint64_t jbytes;  // the jump array: the stream slots, dead once the parse is through
   uint64_t sub_cap;
 };
@@ -2207,9 +2253,9 @@ static Layout make_layout(const Plan& P) {
   L.pcnt = at, at = align256(at + 4 * ((T + 31) / 32 / kPackWords + 1));
   L.plist = at, at = align256(at + 4 * T);
   L.lmap = at, at = align256(at + W * P.slot_b / 8);
+  L.mcov = at, at = align256(at + W * P.slot_b / 8);
   L.ibase = at, at = align256(at + 8 * W);
   L.wlist = at, at = align256(at + W * P.slot_b / 16);                        // one u32 per map word
-  L.wpsum = at, at = align256(at + 4 * (W * P.slot_b / 64 / kJListWords + 1));
   L.amap = at, at = align256(at + W * P.slot_b / 8);
   L.total = at;
   // the jump array (4 B per window position) reuses the four stream slots,
@@ -2472,8 +2518,8 @@ int plan_parse_tokens(Plan* P, void* d_work, uint64_t work_len, hipStream_t s, u
     hipLaunchKernelGGL(k_ans, dim3(4 * W.items), dim3(64), 0, s, aa);
     ParseArgs pa{P->d_jobs, wbl, W.items, W.tok, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                  P->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), reinterpret_cast<uint64_t*>(w + L.tok),
-                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st, 0};
-    hipLaunchKernelGGL(k_parse<OutDirect>, dim3(W.items), dim3(kParseThreads), 0, s, pa);
+                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st, 0, nullptr};
+    hipLaunchKernelGGL((k_parse<OutDirect, false>), dim3(W.items), dim3(kParseThreads), 0, s, pa);
     try {
       tk.resize(2ull * W.tok);
     } catch (const std::bad_alloc&) {
@@ -2677,8 +2723,10 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
     if (ev) (void)hipEventRecord(ev[1], s);
     ParseArgs pa{P->d_jobs, wbl, W.items, W.tok, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                  P->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), reinterpret_cast<uint64_t*>(w + L.tok),
-                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st, 1};
-    hipLaunchKernelGGL(k_parse<O>, dim3(W.items), dim3(kParseThreads), 0, s, pa);
+                 reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st, 1,
+                 P->opt.bulk_rounds <= 1 ? reinterpret_cast<uint16_t*>(w + L.mcov) : nullptr};
+    if (pa.mcov) hipLaunchKernelGGL((k_parse<O, true>), dim3(W.items), dim3(kParseThreads), 0, s, pa);
+    else hipLaunchKernelGGL((k_parse<O, false>), dim3(W.items), dim3(kParseThreads), 0, s, pa);
     if (ev) (void)hipEventRecord(ev[2], s);
     const uint32_t ntok = W.tok;
     const bool jump = P->opt.tail_mode == 0 && copy_mode != AX_COPY_SERIAL;
@@ -2698,21 +2746,23 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
                   reinterpret_cast<uint32_t*>(w + L.pbits), reinterpret_cast<const uint32_t*>(w + L.plist),
                   P->opt.bulk_rounds <= 1 ? last_mark : 0, 1ull << 22, copy_mode == AX_COPY_SERIAL, P->opt.fill_round,
                   P->opt.fill_tail, uint32_t(P->opt.tail_chunks), reinterpret_cast<uint32_t*>(w + L.lit),
-                  reinterpret_cast<uint64_t*>(w + L.lmap), P->slot_b};
+                  reinterpret_cast<uint64_t*>(w + L.lmap), P->slot_b, pa.mcov ? reinterpret_cast<const uint64_t*>(w + L.mcov) : nullptr};
       // pointer jumping over window positions (the deep remainder); the
       // jump array is the stream slots, dead once the parse is through
       JumpArgs ja{P->d_jobs, wbl, W.items, ntok, P->slot_b, ca.tok, ca.tblk, ca.done,
                   reinterpret_cast<uint32_t*>(w + L.lit), reinterpret_cast<uint64_t*>(w + L.lmap),
                   reinterpret_cast<uint64_t*>(w + L.amap), reinterpret_cast<uint32_t*>(w + L.jflags),
                   reinterpret_cast<uint8_t**>(w + L.ibase), uint32_t(__builtin_ctz(P->slot_b)),
-                  nullptr, nullptr, uint32_t(L.sub_cap), reinterpret_cast<uint32_t*>(w + L.wlist),
-                  reinterpret_cast<uint32_t*>(w + L.wpsum), st, 0};
+                  nullptr, nullptr, uint32_t(L.sub_cap), reinterpret_cast<uint32_t*>(w + L.wlist), st, 0};
       const uint64_t mwords = uint64_t(W.items) * (P->slot_b / 64);  // leftover-map words
       // eight listed words per wave step, four waves per workgroup
       const uint32_t jgrid = uint32_t(std::min<uint64_t>((mwords + 31) / 32, kJMaxGrid));
       if (jump) hipLaunchKernelGGL(k_jprep<O>, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
       const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
-      if (P->opt.round0_tile) hipLaunchKernelGGL(k_round0<O>, dim3(W.items), dim3(kCopyThreads), 0, s, ca);
+      if (P->opt.round0_tile && ca.mcov)
+        hipLaunchKernelGGL((k_round0<O, true>), dim3(W.items), dim3(kCopyThreads), 0, s, ca);
+      else if (P->opt.round0_tile)
+        hipLaunchKernelGGL((k_round0<O, false>), dim3(W.items), dim3(kCopyThreads), 0, s, ca);
       else hipLaunchKernelGGL(k_round0_waves<O>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       hipLaunchKernelGGL(k_long<O>, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
       for (int r = 1; r < P->opt.bulk_rounds; ++r) {
@@ -2741,7 +2791,6 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
         ja.lcnt = ca.cnt_out;
         hipLaunchKernelGGL(k_jmarklong<O>, dim3(grid), dim3(kCopyThreads), 0, s, ja);
         const uint32_t lgrid = uint32_t((mwords + kJListWords - 1) / kJListWords);
-        hipLaunchKernelGGL(k_jlcount, dim3(lgrid), dim3(kCopyThreads), 0, s, ja);
         hipLaunchKernelGGL(k_jlist, dim3(lgrid), dim3(kCopyThreads), 0, s, ja);
         hipLaunchKernelGGL(k_jinit, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
         const uint32_t passes = P->opt.jump_passes ? std::min<uint32_t>(P->jpass[wi], P->opt.jump_passes) : P->jpass[wi];
