@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs (DNA, English-like text, batch plans, request traces).
+"""Seeded synthetic inputs (DNA, English-like text, protein-like sequences,
+FASTQ-like reads, batch plans, request traces).
 
 Input generation only: none of the codec's arithmetic lives here, so the
 oracle side and the product side may both use it.  The C generator
@@ -24,6 +25,8 @@ def _load():
         u64p = ctypes.POINTER(ctypes.c_uint64)
         lib.axs_dna.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64]
         lib.axs_text.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64]
+        lib.axs_protein.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64]
+        lib.axs_reads.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64]
         lib.axs_batch_plan.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u64p, u8p]
         lib.axs_trace.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                   ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, u64p, u64p, u64p]
@@ -85,6 +88,22 @@ def text(n, seed):
     return out
 
 
+def protein(n, seed):
+    """Synthetic protein-like sequences, one per line: n bytes."""
+    out = np.empty(int(n), dtype=np.uint8)
+    if _load().axs_protein(_u8(out), int(n), int(seed)) != 0:
+        raise MemoryError("axs_protein")
+    return out
+
+
+def reads(n, seed):
+    """Synthetic FASTQ-like 100-base reads of a synthetic genome: n bytes."""
+    out = np.empty(int(n), dtype=np.uint8)
+    if _load().axs_reads(_u8(out), int(n), int(seed)) != 0:
+        raise MemoryError("axs_reads")
+    return out
+
+
 def batch_plan(count, seed):
     """Sizes (bytes) and kinds (0 DNA, 1 text) of a batch of archives."""
     sizes = np.empty(int(count), dtype=np.uint64)
@@ -114,10 +133,13 @@ WORKLOADS = {
     "dna4": ("dna", 4 * 1024 * 1024, 1),
     "dna254": ("dna", 15500 * 16384, 2),
     "text200": ("text", 209715200, 3),
+    "protein254": ("protein", 15500 * 16384, 6),
+    "reads254": ("reads", 15500 * 16384, 7),
 }
+GENERATORS = {"dna": dna, "text": text, "protein": protein, "reads": reads}
 
 
 def workload_input(name, n=None):
     kind, size, seed = WORKLOADS[name]
     size = size if n is None else n
-    return dna(size, seed) if kind == "dna" else text(size, seed)
+    return GENERATORS[kind](size, seed)

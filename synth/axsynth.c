@@ -257,6 +257,140 @@ int axs_text(uint8_t* out, uint64_t n, uint64_t seed) {
   return 0;
 }
 
+/* -------------------------------------------------------------- proteins --- */
+
+static const uint8_t AMINO[20] = {'A', 'C', 'D', 'E', 'F', 'G', 'H', 'I', 'K', 'L',
+                                  'M', 'N', 'P', 'Q', 'R', 'S', 'T', 'V', 'W', 'Y'};
+
+/* Residue from a cumulative background distribution. */
+static uint8_t amino_draw(const double* cum, uint64_t* s) {
+  double u = u01(s);
+  int k = 0;
+  while (k < 19 && u >= cum[k]) k++;
+  return AMINO[k];
+}
+
+/* Protein-like sequences, one per line: lengths Lognormal(ln 350, 0.6)
+ * clipped to [30, 5000]; residues order-0 from a background drawn once per
+ * seed (Dirichlet(2, ..., 2) over the 20 amino acids).  A new sequence is,
+ * with probability 0.30, a homolog of a uniformly chosen earlier sequence
+ * (each residue substituted with probability 0.15, deleted with 0.01, a
+ * random residue inserted after it with 0.01), with probability 0.05 an
+ * exact duplicate of one, else fresh.  With probability 0.03 a sequence
+ * carries a low-complexity segment: a unit of 1..3 residues repeated to
+ * 10..60 residues at a uniform place. */
+int axs_protein(uint8_t* out, uint64_t n, uint64_t seed) {
+  uint64_t s = seed * 0x2545F4914F6CDD1DULL + 0x632BE59BD9B4E019ULL;
+  double cum[20], t = 0, g[20];
+  for (int k = 0; k < 20; k++) { /* Gamma(2,1) = -ln(u1 u2) */
+    g[k] = -log((1.0 - u01(&s)) * (1.0 - u01(&s)));
+    t += g[k];
+  }
+  double acc = 0;
+  for (int k = 0; k < 20; k++) { acc += g[k] / t; cum[k] = acc; }
+  cum[19] = 1.0;
+  uint64_t cap = 1024, ns = 0;
+  uint64_t* st = (uint64_t*)malloc(cap * sizeof(uint64_t));
+  uint64_t* en = (uint64_t*)malloc(cap * sizeof(uint64_t));
+  if (!st || !en) { free(st); free(en); return -1; }
+  uint64_t pos = 0;
+  while (pos < n) {
+    if (ns == cap) {
+      cap *= 2;
+      uint64_t* a = (uint64_t*)realloc(st, cap * sizeof(uint64_t));
+      uint64_t* b = (uint64_t*)realloc(en, cap * sizeof(uint64_t));
+      if (!a || !b) { free(a ? a : st); free(b ? b : en); return -1; }
+      st = a; en = b;
+    }
+    const uint64_t start = pos;
+    const double u = u01(&s);
+    if (ns > 0 && u < 0.35) {
+      const uint64_t j = unif(&s, 0, ns - 1);
+      const int exact = u >= 0.30;
+      for (uint64_t q = st[j]; q < en[j] && pos < n; q++) {
+        if (exact) { out[pos++] = out[q]; continue; }
+        const double e = u01(&s);
+        if (e < 0.01) continue; /* deletion */
+        out[pos++] = e < 0.16 ? amino_draw(cum, &s) : out[q];
+        if (pos < n && u01(&s) < 0.01) out[pos++] = amino_draw(cum, &s); /* insertion */
+      }
+    } else {
+      double l = floor(lognormal(&s, log(350.0), 0.6) + 0.5);
+      uint64_t len = l < 30 ? 30 : l > 5000 ? 5000 : (uint64_t)l;
+      for (uint64_t k = 0; k < len && pos < n; k++) out[pos++] = amino_draw(cum, &s);
+    }
+    if (pos > start + 60 && u01(&s) < 0.03) { /* low-complexity segment */
+      const unsigned period = (unsigned)unif(&s, 1, 3);
+      uint8_t unit[3];
+      for (unsigned k = 0; k < period; k++) unit[k] = amino_draw(cum, &s);
+      const uint64_t len = unif(&s, 10, 60), at = unif(&s, start, pos - len);
+      for (uint64_t k = 0; k < len; k++) out[at + k] = unit[k % period];
+    }
+    st[ns] = start;
+    en[ns] = pos;
+    ns++;
+    if (pos < n) out[pos++] = '\n';
+  }
+  free(st); free(en);
+  return 0;
+}
+
+/* ----------------------------------------------------------------- reads --- */
+
+/* FASTQ-like sequencing reads of a synthetic genome.  The genome is the DNA
+ * generator's output for this seed (N bases replaced by A, lowercase folded
+ * to uppercase), of max(2^20, n / 32) bases, so the reads cover it about
+ * twelve times.  Record i is "@r<i>/1", a 100-base read from a uniform
+ * genome position (each base substituted with probability 0.005), "+" and
+ * a quality line of Phred+33 symbols: a walk over levels 2..41 starting at
+ * 38 that per base holds (0.5), steps up (0.25) or down (0.2) by one, or
+ * jumps to a uniform level (0.05), and past base 70 drifts one level down
+ * with probability 0.3. */
+int axs_reads(uint8_t* out, uint64_t n, uint64_t seed) {
+  uint64_t s = seed * 0x2545F4914F6CDD1DULL + 0x8CB92BA72F3D8DD7ULL;
+  const uint64_t glen = n / 32 > (1u << 20) ? n / 32 : (1u << 20);
+  uint8_t* g = (uint8_t*)malloc(glen);
+  if (!g) return -1;
+  if (axs_dna(g, glen, seed ^ 0x5EEDull)) { free(g); return -1; }
+  for (uint64_t k = 0; k < glen; k++) g[k] = g[k] == 'N' || g[k] == 'n' ? 'A' : (uint8_t)(g[k] & ~0x20);
+  const unsigned R = 100;
+  uint64_t pos = 0, rec = 0;
+  char head[32];
+  while (pos < n) {
+    int hl = 0;
+    uint64_t v = rec++, d = 1;
+    while (v / d >= 10) d *= 10;
+    head[hl++] = '@';
+    head[hl++] = 'r';
+    for (; d; d /= 10) head[hl++] = (char)('0' + (v / d) % 10);
+    head[hl++] = '/';
+    head[hl++] = '1';
+    head[hl++] = '\n';
+    for (int k = 0; k < hl && pos < n; k++) out[pos++] = (uint8_t)head[k];
+    const uint64_t at = unif(&s, 0, glen - R);
+    for (unsigned k = 0; k < R && pos < n; k++) {
+      uint8_t b = g[at + k];
+      if (u01(&s) < 0.005) b = BASES[(base_code(b) + 1 + unif(&s, 0, 2)) & 3];
+      out[pos++] = b;
+    }
+    if (pos < n) out[pos++] = '\n';
+    if (pos < n) out[pos++] = '+';
+    if (pos < n) out[pos++] = '\n';
+    unsigned q = 38;
+    for (unsigned k = 0; k < R && pos < n; k++) {
+      const double u = u01(&s);
+      if (u >= 0.95) q = (unsigned)unif(&s, 2, 41);
+      else if (u >= 0.75) q = q > 2 ? q - 1 : 2;
+      else if (u >= 0.5) q = q < 41 ? q + 1 : 41;
+      if (k > 70 && q > 2 && u01(&s) < 0.3) q--;
+      out[pos++] = (uint8_t)(33 + q);
+    }
+    if (pos < n) out[pos++] = '\n';
+  }
+  free(g);
+  return 0;
+}
+
 /* ---------------------------------------------------------- batch plan --- */
 
 void axs_batch_plan(uint32_t count, uint64_t seed, uint64_t* sizes, uint8_t* kinds) {

@@ -13,6 +13,9 @@
  *              the Pizza&Chili dna corpus (Setup; Table 2).
  *   axs_text — English-like text (Zipf vocabulary, re-emitted sentences):
  *              stands in for enwik / Pizza&Chili english (Table 2).
+ *   axs_protein, axs_reads — protein-like sequences and FASTQ-like reads,
+ *              the second workload family (Table 2's proteins; the genome
+ *              vs reads depth tails).
  */
 #ifndef AXSYNTH_H
 #define AXSYNTH_H
@@ -26,6 +29,16 @@ int axs_dna(uint8_t* out, uint64_t n, uint64_t seed);
 
 /* Fill out[0..n) with synthetic English-like text for `seed`. 0 / -1 on OOM. */
 int axs_text(uint8_t* out, uint64_t n, uint64_t seed);
+
+/* Fill out[0..n) with protein-like sequences (one per line; 20-letter
+ * alphabet; homologs, duplicates and low-complexity segments): stands in for
+ * the Pizza&Chili proteins corpus (Table 2).  0 / -1 on OOM. */
+int axs_protein(uint8_t* out, uint64_t n, uint64_t seed);
+
+/* Fill out[0..n) with FASTQ-like 100-base reads of a synthetic genome (about
+ * twelvefold coverage, 0.5 % substitutions, Markov quality lines): stands in
+ * for the sequencing-read set of the depth-tail comparison.  0 / -1. */
+int axs_reads(uint8_t* out, uint64_t n, uint64_t seed);
 
 /* Batch plan: for archive i in [0,count): size in bytes and kind (0 = DNA,
  * 1 = text). Sizes are Lognormal(ln 1 MiB, 1.2) clipped to [64 KiB, 64 MiB];

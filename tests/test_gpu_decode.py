@@ -81,6 +81,19 @@ def test_no_rep_encoding():
     check("no_rep", x, arc)
 
 
+@pytest.mark.parametrize("kind", ["protein", "reads"])
+def test_second_workload_family(kind):
+    """Protein-like sequences and FASTQ-like reads, at the small shape (4 MiB,
+    oracle encoder, both copy modes) and at full size (253,952,000 B, the
+    library's encoder, default launch configuration)."""
+    x = synth.GENERATORS[kind](4 << 20, 21)
+    arc, _ = oracle.encode(x)
+    check(f"{kind}-4m", x, arc)
+    x = synth.workload_input(f"{kind}254")
+    arc = ax.encode(x, threads=16)
+    check(f"{kind}-full", x, arc, modes=(ax.COPY_PERIODIC,))
+
+
 def test_full_size_no_rep_dna():
     """The history-free encoding (no REP commands: every match carries its
     offset) of the full-size DNA workload (253,952,000 B, seed 2), in the

@@ -529,3 +529,30 @@ def test_generators_are_deterministic_and_shaped():
     assert 0.15 < low < 0.45  # ~30% lowercase runs
     t = synth.text(100000, 3)
     assert set(np.unique(t).tobytes()) <= set(b"abcdefghijklmnopqrstuvwxyz ,.?!\n")
+
+
+def test_protein_and_read_generators_are_deterministic_and_shaped():
+    p = synth.protein(200000, 6)
+    assert np.array_equal(p, synth.protein(200000, 6))
+    assert not np.array_equal(p, synth.protein(200000, 7))
+    assert set(np.unique(p).tobytes()) <= set(b"ACDEFGHIKLMNPQRSTVWY\n")
+    lines = bytes(p).split(b"\n")[:-1]
+    assert 30 <= np.median([len(s) for s in lines]) <= 2000
+    r = synth.reads(300000, 7)
+    assert np.array_equal(r, synth.reads(300000, 7))
+    recs = bytes(r).split(b"\n")
+    full = (len(recs) - 1) // 4
+    assert full > 100
+    for i in range(full):
+        head, seq, plus, qual = recs[4 * i: 4 * i + 4]
+        assert head == b"@r%d/1" % i and plus == b"+"
+        assert len(seq) == 100 and set(seq) <= set(b"ACGT")
+        assert len(qual) == 100 and all(35 <= q <= 74 for q in qual)
+
+
+@pytest.mark.parametrize("kind", ["protein", "reads"])
+def test_second_family_round_trips_through_the_oracle(kind):
+    x = synth.GENERATORS[kind](3 << 20, 11)
+    arc, st = oracle.encode(x)
+    assert np.array_equal(oracle.decode(arc), x)
+    assert st.n_matches > 0 and x.size / arc.size > 1.2
