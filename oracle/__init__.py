@@ -69,6 +69,7 @@ def lib():
                                         ctypes.c_uint32, u8p, u32p, ctypes.c_uint32, u8p, u32p]
         L.axo_block_parse.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, P(Cmd), ctypes.c_uint64, u64p]
         L.axo_depths.argtypes = [u8p, ctypes.c_uint64, u32p, ctypes.c_uint64, u32p]
+        L.axo_parse_all.argtypes = [u8p, ctypes.c_uint64, P(P(Cmd)), u64p]
         L.axo_block_levels.argtypes = [u8p, ctypes.c_uint64, u32p, u32p, u32p, u32p]
         L.axo_closure.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, u8p, u64p]
         L.axo_stream_encode.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
@@ -210,6 +211,23 @@ def block_parse(arc, block):
     if rc:
         raise OracleError(rc, "block_parse")
     return out[: n.value]
+
+
+def parse_all(arc):
+    """Every command of the archive in output order, as CMD_DTYPE records."""
+    a = _arr(arc)
+    ptr = ctypes.POINTER(Cmd)()
+    n = ctypes.c_uint64()
+    rc = lib().axo_parse_all(_u8(a), a.size, ctypes.byref(ptr), ctypes.byref(n))
+    if rc:
+        raise OracleError(rc, "parse_all")
+    if not n.value:
+        lib().axo_free(ptr)
+        return np.zeros(0, CMD_DTYPE)
+    raw = ctypes.cast(ptr, ctypes.POINTER(ctypes.c_uint8))
+    out = np.ctypeslib.as_array(raw, shape=(n.value * CMD_DTYPE.itemsize,)).copy().view(CMD_DTYPE)
+    lib().axo_free(ptr)
+    return out
 
 
 def depths(arc):

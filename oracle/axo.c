@@ -841,6 +841,10 @@ int axo_block_parse(const uint8_t* arc, uint64_t len, uint64_t block, axo_cmd* c
 }
 
 /* All commands of the archive, in output order. */
+int axo_parse_all(const uint8_t* arc, uint64_t len, axo_cmd** cmds, uint64_t* n_cmds) {
+  return walk_all(arc, len, cmds, n_cmds);
+}
+
 static int walk_all(const uint8_t* arc, uint64_t len, axo_cmd** cmds_out, uint64_t* n_out) {
   axo_info in;
   int rc = axo_read_info(arc, len, &in);

@@ -116,6 +116,10 @@ int axo_block_streams(const uint8_t* arc, uint64_t len, uint64_t block,
 int axo_block_parse(const uint8_t* arc, uint64_t len, uint64_t block, axo_cmd* cmds,
                     uint64_t cap, uint64_t* n_cmds);
 
+/* Every command of the archive in output order (the block parse of each
+ * block, concatenated); *cmds is allocated here, release with axo_free. */
+int axo_parse_all(const uint8_t* arc, uint64_t len, axo_cmd** cmds, uint64_t* n_cmds);
+
 /* Chain depth of every match (MATCH and REP, archive order) and the maximum.
  * depth = 0 when every source byte was written by a literal command, else
  * 1 + the deepest match that wrote a source byte. Source set of a match:

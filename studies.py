@@ -21,8 +21,8 @@ and every byte) before it is timed; inputs are the seeded synthetic corpora.
             at Scale", the reconciling model's F + c * tokens): 16 KiB reads
             by position decile, widths of 1 to 1000 blocks, the least-squares
             fit over all reads, and an equal-token-mass control on a 254 MB
-            archive (closure tokens forced to literals on the deepest chain,
-            the same number of leaf tokens, or none).
+            archive (the read's closure matches above a depth forced to
+            literals, the same number of leaf matches, or none).
 
 Usage: python studies.py {depth,minmatch,corpora,seek} [options]
 """
@@ -294,8 +294,8 @@ def study_seek(args):
 
     # (4) equal-token-mass control on the 254 MB DNA workload: the block whose
     # own matches reach deepest is read whole from three archives of the same
-    # bytes, its closure's deepest matches forced to literals (A), as many
-    # leaf matches (depth 0) forced (B), or none (C)
+    # bytes: its closure's matches deeper than --cut-depth forced to literals
+    # (A), as many leaf matches (depth 0) forced (B), or none (C)
     x = synth.workload_input("dna254")
     arc0 = ax.encode(x, threads=args.threads)
     depth, _ = oracle.depths(arc0)
@@ -306,16 +306,17 @@ def study_seek(args):
     np.maximum.at(deepest, tblk, depth.astype(np.int64))
     tb = int(np.argmax(deepest))
     target = (tb * B, min(B, x.size - tb * B))
-    cmds = np.concatenate([oracle.block_parse(arc0, b) for b in range(nbk)])
+    cmds = oracle.parse_all(arc0)
     mi = np.nonzero(cmds["kind"] > 0)[0]  # command index of match t (archive order)
     dec0 = ax.Decoder(arc0, torch.from_numpy(arc0).to(dev))
     dec0.build_index()
     clo = closure_tokens(dec0, target, mpre)
     del dec0
-    k = max(1, min(args.force, clo.size // 4))
-    deep = clo[np.argsort(-depth[clo], kind="stable")[:k]]
+    # A cuts every chain of the closure above depth `cut_depth`; B forces as
+    # many leaf matches (depth 0), so both remove the same token mass
+    deep = clo[depth[clo] > args.cut_depth]
     leaves = clo[depth[clo] == 0]
-    leaf = leaves[rng.choice(leaves.size, min(k, leaves.size), replace=False)] if leaves.size else leaves
+    leaf = leaves[rng.choice(leaves.size, min(deep.size, leaves.size), replace=False)] if leaves.size else leaves
     control = {}
     for name, pick in (("A_deep", mi[deep]), ("B_leaf", mi[leaf]), ("C_placebo", mi[:0])):
         arc = oracle.assemble(x, force_literals(cmds, pick))
@@ -350,7 +351,7 @@ def main():
     ap.add_argument("--bytes", type=float, default=32 * 2 ** 30, help="seek: archive size")
     ap.add_argument("--per-decile", type=int, default=100)
     ap.add_argument("--per-width", type=int, default=10)
-    ap.add_argument("--force", type=int, default=64, help="seek control: tokens forced to literals")
+    ap.add_argument("--cut-depth", type=int, default=4, help="seek control: closure matches deeper than this are forced")
     ap.add_argument("--control-reps", type=int, default=200)
     args = ap.parse_args()
     defaults = {"depth": "dna254,text200", "minmatch": "dna254,text200",

@@ -556,3 +556,12 @@ def test_second_family_round_trips_through_the_oracle(kind):
     arc, st = oracle.encode(x)
     assert np.array_equal(oracle.decode(arc), x)
     assert st.n_matches > 0 and x.size / arc.size > 1.2
+
+
+def test_parse_all_is_the_block_parses_concatenated():
+    x = synth.dna((5 << 14) + 77, 12)
+    arc, _ = oracle.encode(x)
+    nb = oracle.info(arc).n_blocks
+    want = np.concatenate([oracle.block_parse(arc, b) for b in range(nb)])
+    got = oracle.parse_all(arc)
+    assert got.dtype == oracle.CMD_DTYPE and np.array_equal(got, want)
