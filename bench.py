@@ -530,6 +530,12 @@ def main():
     if err:
         log(f"device status {err} during timing")
         sys.exit(1)
+    # the timed decodes ran what the decoder learned from the first ones
+    # (bulk-round and jump-pass counts): the last one's output is checked too
+    if xxhash.xxh3_64_intdigest(out.cpu().numpy().tobytes()) != want:
+        log("DECODE MISMATCH after timing")
+        print(json.dumps({"metric": METRIC, "value": None, "error": "decode mismatch after timing"}))
+        sys.exit(1)
     ms_per_step = gpu_ms / args.steps
     value = n / (ms_per_step / 1e3) / 1e9
     ans_ms, parse_ms, copy_ms, rem_ms = (stage / args.steps).tolist()

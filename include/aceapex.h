@@ -181,8 +181,10 @@ int aceapex_decoder_set_timing(aceapex_decoder* dec, int enable);
 
 /* Decoder options (schedule knobs; none changes a decoded byte).
  *   AX_OPT_BULK_ROUNDS  number of level-synchronous match-layer rounds (one
- *     launch each, plain cached accesses) before the persistent launch that
- *     finishes the deeper tokens, in [1, 250] (default 4). */
+ *     launch each, plain cached accesses) before the launches that finish the
+ *     deeper tokens, in [1, 250] (default 4).  Until it is set, a decoder
+ *     learns it per window from its first decode: a window whose first round
+ *     fills less than half its matches (a deep archive) runs that round only. */
 enum { AX_OPT_BULK_ROUNDS = 1 };
 /*   AX_OPT_FILL_ROUNDS / AX_OPT_FILL_TAIL  how a wave fills its ready tokens
  *     in the rounds after the first / in the persistent launch: 0 short
@@ -220,6 +222,10 @@ enum { AX_OPT_TAIL_MODE = 7 };
  *     passes.  The final gather follows whatever entries the passes left, so
  *     the count changes timing only, never a byte. */
 enum { AX_OPT_JUMP_PASSES = 8 };
+/*   AX_OPT_RANGE_JUMP_TOKENS  range decodes of this decoder finish closures of
+ *     at least this many matches by pointer jumping, smaller ones by the
+ *     persistent launch (default 65536; 0 = always jump). */
+enum { AX_OPT_RANGE_JUMP_TOKENS = 9 };
 int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
 
 /* The entropy stage alone (Setup: per-block rANS of the LIT, LEN, OFF and

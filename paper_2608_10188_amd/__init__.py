@@ -31,7 +31,7 @@ EXPORTS = [
     "aceapex_range_workspace", "aceapex_decoder_streams", "aceapex_decoder_tokens",
 ]
 OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH, OPT_ROUND0_TILE = 1, 2, 3, 4, 5, 6
-OPT_TAIL_MODE, OPT_JUMP_PASSES = 7, 8
+OPT_TAIL_MODE, OPT_JUMP_PASSES, OPT_RANGE_JUMP_TOKENS = 7, 8, 9
 TAIL_JUMP, TAIL_CHASE = 0, 1
 STATIC_SCRATCH_BYTES = 128 << 20  # AX_STATIC_SCRATCH_BYTES
 

@@ -79,7 +79,8 @@ struct DevStatus {
   uint32_t pad2;
   uint32_t jump_used;    // jump passes that found active entries (0: all of them did)
   uint32_t n_jwords;     // leftover-map words with bits set (the jump kernels' work list)
-  uint32_t pad1[54];
+  uint32_t pend0;        // tokens round 0 left to the later rounds (reported when asked)
+  uint32_t pad1[53];
 };
 static_assert(sizeof(DevStatus) == 256, "status block is 256 bytes");
 
@@ -2125,6 +2126,13 @@ __global__ void k_clear2(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m) {
 }
 
 // Status reset before each window (the first also clears the error word).
+// The tokens round 0 left: the sum of its sublist counters (one wave).
+__global__ void k_pending0(const uint32_t* cnt, DevStatus* st) {
+  uint32_t tot;
+  (void)wave_excl_sum(threadIdx.x < kSub ? cnt[threadIdx.x * kCounterStride] : 0u, &tot);
+  if (threadIdx.x == 0) st->pend0 = tot;
+}
+
 __global__ void k_window_init(DevStatus* st, int first) {
   if (threadIdx.x == 0) {
     if (first) {
@@ -2136,6 +2144,7 @@ __global__ void k_window_init(DevStatus* st, int first) {
     st->n_pending = 0;
     st->jump_used = 0;
     st->n_jwords = 0;
+    st->pend0 = 0;
   }
 }
 
@@ -2190,10 +2199,18 @@ struct Plan {
   // which exits at once and reports it again); the gather finishes any
   // entry the passes leave, so the count never changes a byte
   std::vector<uint32_t> jpass;
-  uint32_t* h_jused = nullptr;   // pinned: per window, passes that found work
+  // pinned: per window, the passes that found work and the tokens round 0
+  // filled (two words)
+  uint32_t* h_jused = nullptr;
   size_t jused_cap = 0;
   hipEvent_t jfed = nullptr;     // h_jused is complete after this
   bool jfeed_pending = false, jsettled = false;
+  // bulk rounds per window, learned from round 0's report when the caller
+  // left the count to the library: a window whose round 0 fills less than
+  // half its tokens (a deep archive) goes straight to the remainder (0: the
+  // configured count)
+  std::vector<uint8_t> wbulk;
+  bool bulk_auto = true, bsettled = false;
   bool learn = true;             // plans rebuilt for every call (ranges) keep the bound
   bool mapped = false;           // one job whose output is a compact scratch addressed by slot
   hipGraphExec_t graph = nullptr;
@@ -2359,6 +2376,8 @@ static int build_tables(Plan* P, const std::vector<JobSpec>& specs) {
     P->jpass.assign(P->wins.size(), 0);
     for (size_t i = 0; i < P->wins.size(); ++i) P->jpass[i] = jump_pass_bound(P->wins[i].tok);
     P->jsettled = false;
+    P->wbulk.assign(P->wins.size(), 0);
+    P->bsettled = false;
   } catch (const std::bad_alloc&) {
     return fail(AX_E_NOMEM, "plan tables");
   }
@@ -2401,7 +2420,7 @@ static int ensure_device(Plan* P) {
     if (P->jfeed_pending) (void)hipEventSynchronize(P->jfed), P->jfeed_pending = false;
     if (P->h_jused) (void)hipHostFree(P->h_jused), P->h_jused = nullptr;
     P->jused_cap = 0;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&P->h_jused), 4 * P->wins.size());
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&P->h_jused), 8 * P->wins.size());
     if (e != hipSuccess) return hip_fail(e, "pass report staging");
     P->jused_cap = P->wins.size();
   }
@@ -2611,6 +2630,8 @@ int plan_set_option(Plan* P, int option, int64_t value) {
     case AX_OPT_BULK_ROUNDS:
       if (value < 1 || value > 250) return fail(AX_E_ARG, "bulk rounds must be in [1, 250]");
       P->opt.bulk_rounds = int(value);
+      P->bulk_auto = false;
+      std::fill(P->wbulk.begin(), P->wbulk.end(), uint8_t(0));
       break;
     case AX_OPT_TAIL_CHUNKS:
       if (value < 1 || value > 64) return fail(AX_E_ARG, "tail chunks must be in [1, 64]");
@@ -2637,6 +2658,10 @@ int plan_set_option(Plan* P, int option, int64_t value) {
       if (value < 0 || value > int64_t(kJPasses)) return fail(AX_E_ARG, "jump passes must be in [0, 32]");
       P->opt.jump_passes = int(value);
       break;
+    case AX_OPT_RANGE_JUMP_TOKENS:
+      if (value < 0 || value > int64_t(kWindowTokens)) return fail(AX_E_ARG, "range jump tokens out of range");
+      P->opt.range_jump_tokens = value;
+      break;
     default:
       return fail(AX_E_ARG, "unknown option");
   }
@@ -2657,6 +2682,7 @@ int plan_get_option(const Plan* P, int option, int64_t* value) {
     case AX_OPT_GRAPH: *value = P->opt.graph; return AX_OK;
     case AX_OPT_TAIL_MODE: *value = P->opt.tail_mode; return AX_OK;
     case AX_OPT_JUMP_PASSES: *value = P->opt.jump_passes; return AX_OK;
+    case AX_OPT_RANGE_JUMP_TOKENS: *value = P->opt.range_jump_tokens; return AX_OK;
     default: return fail(AX_E_ARG, "unknown option");
   }
 }
@@ -2721,10 +2747,11 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
     if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_ans, dim3(4 * W.items), dim3(64), 0, s, aa);
     if (ev) (void)hipEventRecord(ev[1], s);
+    const int bulk = P->wbulk[wi] ? int(P->wbulk[wi]) : P->opt.bulk_rounds;
     ParseArgs pa{P->d_jobs, wbl, W.items, W.tok, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                  P->len_cap, reinterpret_cast<const uint32_t*>(w + L.nsym), reinterpret_cast<uint64_t*>(w + L.tok),
                  reinterpret_cast<uint32_t*>(w + L.tblk), w + L.done, st, 1,
-                 P->opt.bulk_rounds <= 1 ? reinterpret_cast<uint16_t*>(w + L.mcov) : nullptr};
+                 bulk <= 1 ? reinterpret_cast<uint16_t*>(w + L.mcov) : nullptr};
     if (pa.mcov) hipLaunchKernelGGL((k_parse<O, true>), dim3(W.items), dim3(kParseThreads), 0, s, pa);
     else hipLaunchKernelGGL((k_parse<O, false>), dim3(W.items), dim3(kParseThreads), 0, s, pa);
     if (ev) (void)hipEventRecord(ev[2], s);
@@ -2744,7 +2771,7 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
                   w + L.done, nullptr, lists[0], nullptr, cset(0), cset(1), uint32_t(L.sub_cap),
                   reinterpret_cast<uint32_t*>(w + L.llist), &st->long_count, 0, st,
                   reinterpret_cast<uint32_t*>(w + L.pbits), reinterpret_cast<const uint32_t*>(w + L.plist),
-                  P->opt.bulk_rounds <= 1 ? last_mark : 0, 1ull << 22, copy_mode == AX_COPY_SERIAL, P->opt.fill_round,
+                  bulk <= 1 ? last_mark : 0, 1ull << 22, copy_mode == AX_COPY_SERIAL, P->opt.fill_round,
                   P->opt.fill_tail, uint32_t(P->opt.tail_chunks), reinterpret_cast<uint32_t*>(w + L.lit),
                   reinterpret_cast<uint64_t*>(w + L.lmap), P->slot_b, pa.mcov ? reinterpret_cast<const uint64_t*>(w + L.mcov) : nullptr};
       // pointer jumping over window positions (the deep remainder); the
@@ -2765,18 +2792,19 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
         hipLaunchKernelGGL((k_round0<O, false>), dim3(W.items), dim3(kCopyThreads), 0, s, ca);
       else hipLaunchKernelGGL(k_round0_waves<O>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       hipLaunchKernelGGL(k_long<O>, dim3(std::min<uint32_t>(grid, 2048)), dim3(kCopyThreads), 0, s, ca);
-      for (int r = 1; r < P->opt.bulk_rounds; ++r) {
+      if (feedback && bulk > 1) hipLaunchKernelGGL(k_pending0, dim3(1), dim3(64), 0, s, cset(0), st);
+      for (int r = 1; r < bulk; ++r) {
         ca.round = uint32_t(r);
         ca.list_in = lists[(r - 1) & 1];
         ca.list_out = lists[r & 1];
         ca.cnt_in = cset(r - 1);
         ca.cnt_out = cset(r);
         ca.cnt_clear = cset(r + 1);
-        ca.mark = r + 1 == P->opt.bulk_rounds ? last_mark : 0;
+        ca.mark = r + 1 == bulk ? last_mark : 0;
         // later rounds see the previous round's leftovers only
         hipLaunchKernelGGL(k_round<O>, dim3(grid), dim3(kCopyThreads), 0, s, ca);
       }
-      ca.round = uint32_t(P->opt.bulk_rounds);
+      ca.round = uint32_t(bulk);
       if (ev) (void)hipEventRecord(ev[3], s);
       if (!jump) {
         uint32_t* pcnt = reinterpret_cast<uint32_t*>(w + L.pcnt);
@@ -2799,12 +2827,13 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
           hipLaunchKernelGGL(k_jpass, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
         }
         hipLaunchKernelGGL(k_jgather, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
-        if (feedback) (void)hipMemcpyAsync(P->h_jused + wi, &st->jump_used, 4, hipMemcpyDeviceToHost, s);
+        if (feedback) (void)hipMemcpyAsync(P->h_jused + 2 * wi, &st->jump_used, 4, hipMemcpyDeviceToHost, s);
       } else {
         const uint64_t waves = (ntok + 64ull * P->opt.tail_chunks - 1) / (64ull * P->opt.tail_chunks);
         const uint32_t tgrid = uint32_t(std::min<uint64_t>((waves + 3) / 4, uint64_t(P->copy_grid)));
         hipLaunchKernelGGL(k_tail<O>, dim3(tgrid), dim3(kCopyThreads), 0, s, ca);
       }
+      if (feedback) (void)hipMemcpyAsync(P->h_jused + 2 * wi + 1, &st->pend0, 4, hipMemcpyDeviceToHost, s);
     }
     if (ev && !ntok) (void)hipEventRecord(ev[3], s);
     if (ev) (void)hipEventRecord(ev[4], s);
@@ -2842,22 +2871,36 @@ static int run_plan(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hip
   }
   uint8_t* w = static_cast<uint8_t*>(d_work);
   const bool timed = P->timing && P->events_ok;
-  // learned jump-pass counts: take the previous decode's report once it is in
+  // learned bulk-round and jump-pass counts: take the previous decode's
+  // report once it is in (a window whose bulk count changes starts its pass
+  // count over from the bound)
   if (P->jfeed_pending && hipEventQuery(P->jfed) == hipSuccess) {
     P->jfeed_pending = false;
     bool all = true;
     for (size_t i = 0; i < P->wins.size(); ++i) {
-      const uint32_t used = P->h_jused[i];
+      const uint32_t used = P->h_jused[2 * i], pend0 = P->h_jused[2 * i + 1];
+      if (P->bulk_auto && !P->bsettled) {
+        const uint8_t b = 2ull * pend0 > P->wins[i].tok ? 1 : 0;
+        if (b != P->wbulk[i]) {
+          P->wbulk[i] = b;
+          P->jpass[i] = jump_pass_bound(P->wins[i].tok);
+          all = false;
+          continue;
+        }
+      }
       if (used) P->jpass[i] = std::min(P->jpass[i], used + 1);
       else all = false;
     }
+    if (P->bulk_auto) P->bsettled = true;
     P->jsettled = all;
-    P->graph_stale = P->graph != nullptr;  // pass counts changed
+    P->graph_stale = P->graph != nullptr;  // counts changed
   }
   if (P->graph_stale && !no_alloc) (void)hipGraphExecDestroy(P->graph), P->graph = nullptr, P->graph_stale = false;
-  const bool feedback = P->learn && !P->jsettled && !P->jfeed_pending && P->opt.tail_mode == 0 && !P->opt.jump_passes &&
-                        copy_mode != AX_COPY_SERIAL && !P->wins.empty() && P->jused_cap >= P->wins.size() && P->jfed;
-  if (feedback) std::fill(P->h_jused, P->h_jused + P->wins.size(), 0u);
+  const bool fb_jump = !P->jsettled && P->opt.tail_mode == 0 && !P->opt.jump_passes && copy_mode != AX_COPY_SERIAL;
+  const bool fb_bulk = P->bulk_auto && !P->bsettled;
+  const bool feedback = P->learn && (fb_jump || fb_bulk) && !P->jfeed_pending && !P->wins.empty() &&
+                        P->jused_cap >= P->wins.size() && P->jfed;
+  if (feedback) std::fill(P->h_jused, P->h_jused + 2 * P->wins.size(), 0u);
   if (P->opt.graph && !timed && !no_alloc) {
     // the launch sequence of every window and round, captured once and replayed
     if (!P->graph || P->graph_work != d_work || P->graph_mode != copy_mode) {

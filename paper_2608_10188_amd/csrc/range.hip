@@ -265,10 +265,10 @@ namespace {
 // Decode the union closure of n ranges with a range plan into its compact
 // scratch and gather each range to its output (everything after the host
 // closure is asynchronous on s).
-// Closures of fewer matches finish their deep remainder with the persistent
-// chase (few launches; their chains are short), larger ones by pointer
-// jumping (a deep closure's chains are long).
-constexpr uint64_t kRangeJumpTokens = 1u << 16;
+// Closures of fewer matches than the decoder's AX_OPT_RANGE_JUMP_TOKENS
+// finish their deep remainder with the persistent chase (few launches; their
+// chains are short), larger ones by pointer jumping (a deep closure's chains
+// are long).
 
 int run_ranges(aceapex_range_plan* rp, const RangeLayout& lay, uint32_t n, const uint64_t* offs,
                const uint64_t* lens, uint8_t* const* d_outs, const uint64_t* out_caps, void* d_work,
@@ -307,7 +307,9 @@ int run_ranges(aceapex_range_plan* rp, const RangeLayout& lay, uint32_t n, const
     }
     if (rc) return rc;
     ax::plan_copy_options(rp->plan, d->plan);
-    rc = ax::plan_set_option(rp->plan, AX_OPT_TAIL_MODE, tok >= kRangeJumpTokens ? 0 : 1);
+    int64_t jump_from = 0;
+    (void)ax::plan_get_option(d->plan, AX_OPT_RANGE_JUMP_TOKENS, &jump_from);
+    rc = ax::plan_set_option(rp->plan, AX_OPT_TAIL_MODE, int64_t(tok) >= jump_from ? 0 : 1);
     if (!rc) rc = ax::plan_set_slots(rp->plan, slot, s);
     if (!rc) rc = ax::plan_run(rp->plan, d_work, lay.plan, copy_mode, s);
     if (rc) return rc;

@@ -250,10 +250,19 @@ def study_seek(args):
     # (1)-(3) on a large archive
     n = int(args.bytes)
     t0 = time.time()
-    x = synth.dna_segmented(n, 5, threads=16)
+    marks = set()
+
+    def progress(done, total, what):
+        g = done * 8 // max(1, total)
+        if (what, g) not in marks:
+            marks.add((what, g))
+            log(f"{what} {done >> 20} of {total >> 20} MiB in {time.time() - t0:.0f}s")
+
+    x = synth.dna_segmented(n, 5, threads=16, progress=lambda d, t: progress(d, t, "generated"))
     log(f"generated {n} B in {time.time() - t0:.1f}s")
     t0 = time.time()
-    arc = ax.encode(x, window_log=30 if n >= (1 << 32) else 0, threads=args.threads)
+    arc = ax.encode(x, window_log=30 if n >= (1 << 32) else 0, threads=args.threads,
+                    progress=lambda d, t: progress(d, t, "encoded"))
     log(f"encoded to {arc.size} B in {time.time() - t0:.1f}s")
     dec = ax.Decoder(arc, torch.from_numpy(arc).to(dev))
     dec.build_index()

@@ -29,8 +29,9 @@ def gpu_decode(arc, copy_mode=ax.COPY_PERIODIC, repeats=1):
     dec = ax.Decoder(arc, d_arc)
     n = int(dec.info.n_bytes)
     outs = []
+    out = torch.empty((max(16, n),), dtype=torch.uint8, device="cuda")
     for _ in range(repeats):
-        out = torch.full((max(16, n),), 0xCC, dtype=torch.uint8, device="cuda")
+        out.fill_(0xCC)
         dec.decode_all(out=out, copy_mode=copy_mode)
         err, bad = dec.status()
         outs.append((err, bad, out[:n].cpu().numpy()))
@@ -38,17 +39,20 @@ def gpu_decode(arc, copy_mode=ax.COPY_PERIODIC, repeats=1):
 
 
 def check(name, x, arc, modes=(ax.COPY_PERIODIC, ax.COPY_SERIAL)):
+    """Every mode decodes three times with one decoder (the first decode
+    teaches the decoder its bulk-round and jump-pass counts; the later ones
+    run what it learned); every output must equal the oracle's decode."""
     x = np.frombuffer(bytes(x), np.uint8) if isinstance(x, (bytes, bytearray)) else x
     ref = oracle.decode(arc)
     assert np.array_equal(ref, x), f"{name}: oracle round trip failed"
     for m in modes:
         _say(name, "copy_mode", m, "n", x.size)
-        err, bad, got = gpu_decode(arc, m)
-        assert err == 0, f"{name}: device status {err} at block {bad}"
-        if not np.array_equal(got, ref):
-            i = int(np.nonzero(got != ref)[0][0])
-            raise AssertionError(f"{name} mode {m}: first mismatch at byte {i} (block {i // B}) "
-                                 f"got {got[i]} want {ref[i]}")
+        for k, (err, bad, got) in enumerate(gpu_decode(arc, m, repeats=3)):
+            assert err == 0, f"{name}: decode {k}: device status {err} at block {bad}"
+            if not np.array_equal(got, ref):
+                i = int(np.nonzero(got != ref)[0][0])
+                raise AssertionError(f"{name} mode {m} decode {k}: first mismatch at byte {i} (block {i // B}) "
+                                     f"got {got[i]} want {ref[i]}")
 
 
 @pytest.mark.parametrize("kind", ["dna", "text"])
