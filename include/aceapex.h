@@ -184,7 +184,8 @@ int aceapex_decoder_set_timing(aceapex_decoder* dec, int enable);
  *     launch each, plain cached accesses) before the launches that finish the
  *     deeper tokens, in [1, 250] (default 4).  Until it is set, a decoder
  *     learns it per window from its first decode: a window whose first round
- *     fills less than half its matches (a deep archive) runs that round only. */
+ *     fills less than a tenth of its matches (a deep archive) runs that round
+ *     only. */
 enum { AX_OPT_BULK_ROUNDS = 1 };
 /*   AX_OPT_FILL_ROUNDS / AX_OPT_FILL_TAIL  how a wave fills its ready tokens
  *     in the rounds after the first / in the persistent launch: 0 short

@@ -2206,9 +2206,9 @@ struct Plan {
   hipEvent_t jfed = nullptr;     // h_jused is complete after this
   bool jfeed_pending = false, jsettled = false;
   // bulk rounds per window, learned from round 0's report when the caller
-  // left the count to the library: a window whose round 0 fills less than
-  // half its tokens (a deep archive) goes straight to the remainder (0: the
-  // configured count)
+  // left the count to the library: a window whose round 0 fills less than a
+  // tenth of its tokens (a deep archive) goes straight to the remainder (0:
+  // the configured count)
   std::vector<uint8_t> wbulk;
   bool bulk_auto = true, bsettled = false;
   bool learn = true;             // plans rebuilt for every call (ranges) keep the bound
@@ -2880,7 +2880,7 @@ static int run_plan(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hip
     for (size_t i = 0; i < P->wins.size(); ++i) {
       const uint32_t used = P->h_jused[2 * i], pend0 = P->h_jused[2 * i + 1];
       if (P->bulk_auto && !P->bsettled) {
-        const uint8_t b = 2ull * pend0 > P->wins[i].tok ? 1 : 0;
+        const uint8_t b = 10ull * pend0 > 9ull * P->wins[i].tok ? 1 : 0;
         if (b != P->wbulk[i]) {
           P->wbulk[i] = b;
           P->jpass[i] = jump_pass_bound(P->wins[i].tok);
