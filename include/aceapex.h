@@ -225,7 +225,7 @@ enum { AX_OPT_TAIL_MODE = 7 };
 enum { AX_OPT_JUMP_PASSES = 8 };
 /*   AX_OPT_RANGE_JUMP_TOKENS  range decodes of this decoder finish closures of
  *     at least this many matches by pointer jumping, smaller ones by the
- *     persistent launch (default 65536; 0 = always jump). */
+ *     persistent launch (default 4096; 0 = always jump). */
 enum { AX_OPT_RANGE_JUMP_TOKENS = 9 };
 int aceapex_decoder_set_option(aceapex_decoder* dec, int option, int64_t value);
 

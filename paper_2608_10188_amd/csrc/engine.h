@@ -22,7 +22,7 @@ struct PlanOptions {
   int graph = 0;        // replay the launch sequence from a captured hipGraph
   int tail_mode = 0;    // deep remainder: pointer jumping (0) or the persistent chase (1)
   int jump_passes = 0;  // at most this many jump passes per window (0: automatic)
-  int64_t range_jump_tokens = 65536;  // range decodes: closures of at least this many matches jump
+  int64_t range_jump_tokens = 4096;  // range decodes: closures of at least this many matches jump
 };
 
 // One archive to decode: all blocks (blocks empty) or the listed blocks
