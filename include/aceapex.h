@@ -210,15 +210,15 @@ enum { AX_OPT_ROUND0_TILE = 6 };
 /*   AX_OPT_TAIL_MODE  how the tokens left after the bulk rounds (the deep
  *     remainder) are finished: 0 = pointer jumping over their bytes — every
  *     byte names the byte its value comes from, and each of about
- *     log2(chain length) passes replaces that name by the one it names
- *     (default); 1 = one persistent launch that copies each token once the
+ *     log3(chain length) passes replaces that name by the one two steps
+ *     along its chain (default); 1 = one persistent launch that copies each token once the
  *     tokens writing its sources are done (one dependency hop at a time; the
  *     serial copy mode always finishes this way).  Range decodes choose by
- *     their closure: the persistent launch below 65536 matches, jumping
- *     above. */
+ *     their closure: the persistent launch below AX_OPT_RANGE_JUMP_TOKENS
+ *     matches (4096 by default), jumping above. */
 enum { AX_OPT_TAIL_MODE = 7 };
 /*   AX_OPT_JUMP_PASSES  0 = automatic: the first decode runs enough passes
- *     for any chain of the window (log2 of its token count) and later ones the
+ *     for any chain of the window (log3 of its token count) and later ones the
  *     count the device reported as needed, plus one; k in [1, 32] = at most k
  *     passes.  The final gather follows whatever entries the passes left, so
  *     the count changes timing only, never a byte. */
