@@ -294,6 +294,14 @@ int aceapex_decoder_build_index(aceapex_decoder* dec, void* d_work, uint64_t wor
 int aceapex_decoder_tokens(const aceapex_decoder* dec, uint64_t first, uint64_t count, uint64_t* src, uint64_t* dst,
                            uint32_t* len);
 
+/* Source-closure size of each of n ranges on its own (blocks and matches),
+ * on up to `threads` host threads (0: up to 16): what a request needs from a
+ * range plan's limits, for admission by scratch memory before any launch.
+ * The sizes of several ranges bound the size of their union.  Errors:
+ * AX_E_ARG (index not built), AX_E_RANGE. */
+int aceapex_closure_sizes(const aceapex_decoder* dec, uint32_t n, const uint64_t* offs, const uint64_t* lens,
+                          uint64_t* blocks, uint64_t* tokens, uint32_t threads);
+
 /* Byte-precise source closure of n ranges: the ascending union of the blocks
  * holding any byte the ranges need (their own bytes and, transitively, the
  * bytes their matches copy).  blocks may be NULL to only count; *n_tokens

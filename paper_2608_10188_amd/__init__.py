@@ -29,6 +29,7 @@ EXPORTS = [
     "aceapex_decoder_build_index", "aceapex_closure_blocks", "aceapex_range_plan_create", "aceapex_range_plan_destroy",
     "aceapex_range_plan_workspace", "aceapex_range_plan_last", "aceapex_decode_ranges", "aceapex_decode_range",
     "aceapex_range_workspace", "aceapex_decoder_streams", "aceapex_decoder_tokens",
+    "aceapex_closure_sizes",
 ]
 OPT_BULK_ROUNDS, OPT_FILL_ROUNDS, OPT_FILL_TAIL, OPT_TAIL_CHUNKS, OPT_GRAPH, OPT_ROUND0_TILE = 1, 2, 3, 4, 5, 6
 OPT_TAIL_MODE, OPT_JUMP_PASSES, OPT_RANGE_JUMP_TOKENS = 7, 8, 9
@@ -112,6 +113,7 @@ def _load():
     u64p = P(u64)
     L.aceapex_decoder_build_index.argtypes = [vp, vp, u64, vp]
     L.aceapex_closure_blocks.argtypes = [vp, ctypes.c_uint32, u64p, u64p, u64p, u64, u64p, u64p, ctypes.c_uint32]
+    L.aceapex_closure_sizes.argtypes = [vp, ctypes.c_uint32, u64p, u64p, u64p, u64p, ctypes.c_uint32]
     L.aceapex_range_plan_create.argtypes = [vp, u64, u64, P(vp)]
     L.aceapex_range_plan_destroy.argtypes = [vp]
     L.aceapex_range_plan_destroy.restype = None
@@ -319,6 +321,18 @@ class Decoder:
                                               ln.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))), "decoder_tokens")
         c = int(count)
         return src[:c], dst[:c], ln[:c]
+
+    def closure_sizes(self, offs, lens, threads=0):
+        """Closure size of each range on its own: (blocks, matches) arrays."""
+        o = np.ascontiguousarray(offs, dtype=np.uint64)
+        ln = np.ascontiguousarray(lens, dtype=np.uint64)
+        nb = np.zeros(max(1, o.size), np.uint64)
+        nt = np.zeros(max(1, o.size), np.uint64)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        _check(_load().aceapex_closure_sizes(self._h, o.size, o.ctypes.data_as(u64p), ln.ctypes.data_as(u64p),
+                                             nb.ctypes.data_as(u64p), nt.ctypes.data_as(u64p), threads),
+               "closure_sizes")
+        return nb[: o.size], nt[: o.size]
 
     def closure_blocks(self, offs, lens, threads=0, want_blocks=True):
         """Union source closure of ranges: (ascending block array, match count)."""

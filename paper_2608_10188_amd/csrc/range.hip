@@ -13,8 +13,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
-#include <map>
+#include <unordered_map>
 #include <new>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -63,24 +64,43 @@ class NeedSet {
     if (open) fresh.emplace_back(run0, b);
   }
 
-  // Ascending list of touched blocks.
+  // Ascending list of touched blocks (appended to out).
   void blocks(std::vector<uint64_t>& out) const {
+    const size_t at = out.size();
     for (const auto& kv : slot_) out.push_back(kv.first);
+    std::sort(out.begin() + at, out.end());
   }
+  size_t count() const { return slot_.size(); }
 
  private:
   uint64_t* bitmap(uint64_t blk) {
+    if (blk == last_blk_) return pool_.data() + last_at_;  // runs of lookups hit one block
     auto it = slot_.find(blk);
     if (it == slot_.end()) {
       it = slot_.emplace(blk, pool_.size()).first;
       pool_.resize(pool_.size() + words_, 0);
     }
+    last_blk_ = blk;
+    last_at_ = it->second;
     return pool_.data() + it->second;
   }
   uint64_t B_, words_;
-  std::map<uint64_t, size_t> slot_;
+  std::unordered_map<uint64_t, size_t> slot_;
   std::vector<uint64_t> pool_;
+  uint64_t last_blk_ = ~0ull;
+  size_t last_at_ = 0;
 };
+
+// Host threads for the closures of n ranges: one per 8 ranges when they are
+// short (a closure takes microseconds, starting a thread tens of them), one
+// per range of at least 64 KiB (its closure takes milliseconds), 16 at most
+// by default (the process may see more cores than its share).
+uint32_t closure_threads(uint32_t n, const uint64_t* lens, uint32_t threads) {
+  uint32_t big = 0;
+  for (uint32_t i = 0; i < n; ++i) big += lens[i] >= (64u << 10);
+  const uint32_t cap = threads ? threads : std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+  return std::max(1u, std::min({cap, std::max((n + 7) / 8, big), 64u}));
+}
 
 // Closure of one range: every position whose byte the range's bytes depend
 // on, found by following each needed match byte to its source.
@@ -127,11 +147,7 @@ int union_closure(const aceapex_decoder* d, uint32_t n, const uint64_t* offs, co
   for (uint32_t i = 0; i < n; ++i)
     if (offs[i] > N || lens[i] > N - offs[i]) return ax::fail(AX_E_RANGE, "range outside the archive");
   if (d->idx_dstlen.size() != d->info.n_matches) return ax::fail(AX_E_ARG, "token index not built");
-  // a thread per 8 ranges at most, 16 at most by default: a closure takes
-  // microseconds, starting a thread tens of them, and the process may see
-  // more cores than its share
-  const uint32_t T = std::max(1u, std::min({threads ? threads : std::min(16u, std::thread::hardware_concurrency()),
-                                            (n + 7) / 8, 64u}));
+  const uint32_t T = closure_threads(n, lens, threads);
   std::vector<std::vector<uint64_t>> part(T);
   std::atomic<uint32_t> next{0};
   auto worker = [&](uint32_t w) {
@@ -370,6 +386,49 @@ int aceapex_decoder_tokens(const aceapex_decoder* d, uint64_t first, uint64_t co
     len[i] = uint32_t(w >> 48) + 1;
   }
   return AX_OK;
+}
+
+int aceapex_closure_sizes(const aceapex_decoder* d, uint32_t n, const uint64_t* offs, const uint64_t* lens,
+                          uint64_t* blocks, uint64_t* tokens, uint32_t threads) {
+  if (!d || (n && (!offs || !lens || !blocks || !tokens))) return ax::fail(AX_E_ARG, "null argument");
+  const uint64_t N = d->info.n_bytes;
+  for (uint32_t i = 0; i < n; ++i)
+    if (offs[i] > N || lens[i] > N - offs[i]) return ax::fail(AX_E_RANGE, "range outside the archive");
+  if (d->idx_dstlen.size() != d->info.n_matches) return ax::fail(AX_E_ARG, "token index not built");
+  const uint32_t T = closure_threads(n, lens, threads);
+  std::atomic<uint32_t> next{0};
+  std::atomic<int> failed{0};
+  auto worker = [&]() {
+    std::vector<uint64_t> bl;
+    for (;;) {
+      const uint32_t i = next.fetch_add(1);
+      if (i >= n) break;
+      bl.clear();
+      if (lens[i]) {
+        try {
+          NeedSet need(d->info.block_size);
+          closure_of(d, offs[i], lens[i], need);
+          need.blocks(bl);
+        } catch (const std::bad_alloc&) {
+          failed = 1;
+          break;
+        }
+      }
+      uint64_t t = 0;
+      for (uint64_t b : bl) t += d->mpre[b + 1] - d->mpre[b];
+      blocks[i] = bl.size();
+      tokens[i] = t;
+    }
+  };
+  try {
+    std::vector<std::thread> pool;
+    for (uint32_t w = 1; w < T; ++w) pool.emplace_back(worker);
+    worker();
+    for (auto& t : pool) t.join();
+  } catch (const std::system_error&) {
+    return ax::fail(AX_E_NOMEM, "closure threads");
+  }
+  return failed ? ax::fail(AX_E_NOMEM, "closure") : AX_OK;
 }
 
 int aceapex_closure_blocks(aceapex_decoder* d, uint32_t n, const uint64_t* offs, const uint64_t* lens,

@@ -90,12 +90,17 @@ class Server:
         t0 = time.perf_counter_ns()
         while completed < n:
             now = time.perf_counter_ns() - t0
-            while nxt < n and (not realtime or arrivals[nxt] <= now):
-                size[nxt] = self.closure_size(int(offs[nxt]), int(lens[nxt]))
-                if size[nxt][0] > self.max_blocks or size[nxt][1] > self.max_tokens:
-                    raise ValueError(f"request {nxt}: closure {size[nxt]} exceeds a slot's limits")
-                queue.append(nxt)
-                nxt += 1
+            arrived = nxt
+            while arrived < n and (not realtime or arrivals[arrived] <= now):
+                arrived += 1
+            if arrived > nxt:  # the closure sizes of all new arrivals, in one parallel call
+                nb, nt = self.dec.closure_sizes(offs[nxt:arrived], lens[nxt:arrived])
+                for k in range(arrived - nxt):
+                    size[nxt + k] = (int(nb[k]), int(nt[k]))
+                    if size[nxt + k][0] > self.max_blocks or size[nxt + k][1] > self.max_tokens:
+                        raise ValueError(f"request {nxt + k}: closure {size[nxt + k]} exceeds a slot's limits")
+                    queue.append(nxt + k)
+                nxt = arrived
             for slot in list(inflight):
                 ev, ids = inflight[slot]
                 if ev.query():

@@ -52,10 +52,13 @@ def test_closure_matches_oracle(kind, dna_archive):
         arc, _ = oracle.encode(x)
     _say("closure", kind)
     d = _decoder_with_index(arc)
-    for off, ln in _ranges(x.size, 40, 7):
+    rs = _ranges(x.size, 40, 7)
+    sizes, _ = d.closure_sizes([r[0] for r in rs], [r[1] for r in rs])
+    for (off, ln), size in zip(rs, sizes):
         mask, k = oracle.closure(arc, off, ln)
         blocks, ntok, nb = d.closure_blocks([off], [ln])
         assert nb == k and np.array_equal(np.nonzero(mask)[0].astype(np.uint64), blocks), (off, ln)
+        assert size == k, (off, ln)
 
 
 def test_union_closure_is_union(dna_archive):
