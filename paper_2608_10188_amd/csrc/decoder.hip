@@ -1873,8 +1873,8 @@ __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
 
 // The work list: the leftover-map words with bits set, in one pass (each
 // workgroup takes kJListWords words, finds its busy ones and appends them at
-// a place reserved with one atomic add: ascending within a workgroup, in any
-// order across them).  When more than a quarter of the map's words are busy
+// a place reserved with one atomic add; the list is in no particular order,
+// which the walks below do not need).  When more than a quarter of the map's words are busy
 // the kernels below walk the whole map instead (dense).
 constexpr uint32_t kJListWords = 16 * kCopyThreads;
 __device__ inline bool jump_dense(const JumpArgs& a, uint32_t n_words) {
@@ -1886,11 +1886,11 @@ __global__ __launch_bounds__(kCopyThreads) void k_jlist(JumpArgs a) {
   __shared__ uint32_t base;
   if (jump_failed(a.st)) return;
   const uint64_t words = uint64_t(a.n_items) * (a.S / 64), w0 = uint64_t(blockIdx.x) * kJListWords;
-  constexpr uint32_t kPer = kJListWords / kCopyThreads;  // consecutive words per thread
+  constexpr uint32_t kPer = kJListWords / kCopyThreads;  // words per thread, kCopyThreads apart (coalesced reads)
   uint32_t bits = 0, c = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kPer; ++q) {
-    const uint64_t g = w0 + kPer * threadIdx.x + q;
+    const uint64_t g = w0 + q * kCopyThreads + threadIdx.x;
     if (g < words && a.lmap[g] != 0) bits |= 1u << q, ++c;
   }
   uint32_t tot;
@@ -1908,7 +1908,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_jlist(JumpArgs a) {
   while (bits) {
     const uint32_t q = __builtin_ctz(bits);
     bits &= bits - 1;
-    a.wlist[at++] = uint32_t(w0 + kPer * threadIdx.x + q);
+    a.wlist[at++] = uint32_t(w0 + q * kCopyThreads + threadIdx.x);
   }
 }
 
