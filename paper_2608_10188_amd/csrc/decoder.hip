@@ -1816,8 +1816,8 @@ __global__ __launch_bounds__(kCopyThreads) void k_jprep(JumpArgs a) {
   }
 }
 
-// Long pending tokens: one wave per token, eight bytes per lane (first
-// entries as in the marking of a round, bits by global atomics).
+// Long pending tokens: one workgroup per token, eight bytes per thread per
+// pass (first entries as in the marking of a round, bits by global atomics).
 template <class O>
 __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
   __shared__ uint32_t sub_end[kSub];  // inclusive prefix of the sublist lengths
@@ -1828,11 +1828,10 @@ __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
     sub_end[threadIdx.x] = wave_excl_sum(c, &tot) + c;
   }
   __syncthreads();
-  const uint32_t n = sub_end[kSub - 1], lane = lane_id();
+  const uint32_t n = sub_end[kSub - 1], lane = threadIdx.x;  // the workgroup's lanes share a token
   AX_GLOBAL uint32_t* const J = gp(a.J);
   uint32_t* const lm32 = reinterpret_cast<uint32_t*>(a.lmap);
-  const uint32_t waves = gridDim.x * (kCopyThreads / 64);
-  for (uint32_t i = blockIdx.x * (kCopyThreads / 64) + (threadIdx.x >> 6); i < n; i += waves) {
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
     uint32_t sl = 0;  // sublist holding item i
 #pragma unroll
     for (uint32_t step = 32; step; step >>= 1)
@@ -1850,7 +1849,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
     uint64_t cb = ~0ull;  // the source block last looked up, kept over the lane's passes
     uint32_t cbase = 0;
     bool cin = false;
-    for (uint32_t k0 = lane * kJMarkBytes; k0 < len; k0 += 64 * kJMarkBytes) {
+    for (uint32_t k0 = lane * kJMarkBytes; k0 < len; k0 += kCopyThreads * kJMarkBytes) {
       uint64_t j = dist > k0 ? k0 : uint64_t(k0 % uint32_t(dist));
       uint32_t mw = ~0u, mbits = 0;
       for (uint32_t k = k0; k < k0 + kJMarkBytes && k < len; ++k) {
