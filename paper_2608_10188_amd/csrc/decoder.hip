@@ -1291,7 +1291,10 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t tile[kMaxB];
   __shared__ uint32_t dirty[kMaxB / 16 / 32];  // chunks of the tile that receive match bytes
   __shared__ uint32_t rdy[kMaxB / 32];         // the block's tokens filled here (min_match >= 1)
-  __shared__ uint32_t lft[kMaxB / 32];         // the block's tokens left pending (marked for jumping)
+  // the block's tokens left pending, marked for jumping when round 0 is the
+  // only round (the coverage-map instantiation; the other one keeps its LDS
+  // for one more resident workgroup)
+  __shared__ uint32_t lft[kCovMap ? kMaxB / 32 : 1];
   if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const uint32_t lane = lane_id(), item = xcd_item(blockIdx.x, gridDim.x);
   if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
@@ -1307,7 +1310,10 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   const uint32_t ntb = t1 - wb.tok;  // <= blen: tokens are at least a byte long
   // the serial ablation reads in-block sources back from the tile: load all of it
   for (uint32_t k = threadIdx.x; k < kMaxB / 16 / 32; k += kCopyThreads) dirty[k] = a.serial ? ~0u : 0u;
-  for (uint32_t k = threadIdx.x; k < (ntb + 31) / 32; k += kCopyThreads) rdy[k] = lft[k] = 0;
+  for (uint32_t k = threadIdx.x; k < (ntb + 31) / 32; k += kCopyThreads) {
+    rdy[k] = 0;
+    if (kCovMap) lft[k] = 0;
+  }
   __syncthreads();
   for (uint32_t base = wb.tok; base < t1; base += kCopyThreads) {
     const uint32_t t = base + threadIdx.x;
@@ -1350,7 +1356,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
     const bool left = act && !ready;
     if (a.mark) {  // the only round: leftovers stay pending (listed, or marked after the fills)
       if (left && a.mark == kMarkList) atomicOr(a.pbits + (t >> 5), 1u << (t & 31));
-      if (left && a.mark == kMarkJump) atomicOr(&lft[(t - wb.tok) >> 5], 1u << ((t - wb.tok) & 31));
+      if (kCovMap && left && a.mark == kMarkJump) atomicOr(&lft[(t - wb.tok) >> 5], 1u << ((t - wb.tok) & 31));
       continue;
     }
     // a wave's tokens fall in at most two 64-token groups, hence two sublists
@@ -1445,7 +1451,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       for (uint32_t i = 16 * k; i < blen; ++i) ob[i] = tile[i];
     }
   }
-  if (a.mark != kMarkJump) return;
+  if (!kCovMap || a.mark != kMarkJump) return;
   // the block's pending tokens, marked for pointer jumping: the tile's bytes
   // now hold the block's leftover-map row and the waves' stages
   __syncthreads();
