@@ -24,7 +24,12 @@ and every byte) before it is timed; inputs are the seeded synthetic corpora.
             archive (the read's closure matches above a depth forced to
             literals, the same number of leaf matches, or none).
 
-Usage: python studies.py {depth,minmatch,corpora,seek} [options]
+  streamdiff  (host only) the depth cap's stream-diff invariant at full size
+            with the oracle encoder: the blocks whose payloads differ between
+            the uncapped and capped archives are exactly those holding a
+            forced position.
+
+Usage: python studies.py {depth,minmatch,corpora,seek,streamdiff} [options]
 """
 import argparse
 import json
@@ -348,9 +353,41 @@ def study_seek(args):
                                         "control": control}})
 
 
+# ------------------------------------------------------------ streamdiff ---
+
+def study_streamdiff(args):
+    """The depth cap's stream-diff invariant at full size, on the host (no
+    GPU): with the oracle encoder, the blocks whose payload bytes differ
+    between the uncapped and the capped archive are exactly the blocks that
+    hold a forced position, and both archives decode to the input."""
+    import oracle
+    import synth
+
+    for wl in args.workloads.split(","):
+        x = synth.workload_input(wl)
+        for L in [int(c) for c in args.caps.split(",") if int(c)]:
+            t0 = time.time()
+            a0, _ = oracle.encode(x)
+            a1, st, forced = oracle.encode_forced(x, depth_cap=L)
+            nb = int(oracle.info(a0).n_blocks)
+            o0 = np.frombuffer(a0[64: 64 + 8 * (nb + 1)].tobytes(), "<u8").astype(np.int64)
+            o1 = np.frombuffer(a1[64: 64 + 8 * (nb + 1)].tobytes(), "<u8").astype(np.int64)
+            h0, h1 = 64 + 16 * (nb + 1), 64 + 16 * (nb + 1)
+            differ = np.array([not np.array_equal(a0[h0 + o0[b]: h0 + o0[b + 1]], a1[h1 + o1[b]: h1 + o1[b + 1]])
+                               for b in range(nb)])
+            pad = np.zeros(nb * B, np.uint8)
+            pad[: x.size] = forced
+            holds = pad.reshape(nb, B).any(axis=1)
+            ok = bool(np.array_equal(oracle.decode(a1), x))
+            emit({"study": "streamdiff", "workload": wl, "cap": L, "blocks": nb, "forced_bytes": int(forced.sum()),
+                  "blocks_with_forced": int(holds.sum()), "blocks_differing": int(differ.sum()),
+                  "invariant": bool(np.array_equal(differ, holds)), "capped_max_depth": int(st.max_depth),
+                  "decodes_to_input": ok, "seconds": round(time.time() - t0, 1)})
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("study", choices=["depth", "minmatch", "corpora", "seek"])
+    ap.add_argument("study", choices=["depth", "minmatch", "corpora", "seek", "streamdiff"])
     ap.add_argument("--workloads", default=None)
     ap.add_argument("--caps", default="0,64,32,24,16")
     ap.add_argument("--min-matches", default="4,6,8,12,16,24,32")
@@ -364,10 +401,11 @@ def main():
     ap.add_argument("--control-reps", type=int, default=200)
     args = ap.parse_args()
     defaults = {"depth": "dna254,text200", "minmatch": "dna254,text200",
-                "corpora": "dna254,text200,protein254,reads254", "seek": ""}
+                "corpora": "dna254,text200,protein254,reads254", "seek": "", "streamdiff": "dna254"}
     if args.workloads is None:
         args.workloads = defaults[args.study]
-    {"depth": study_depth, "minmatch": study_minmatch, "corpora": study_corpora, "seek": study_seek}[args.study](args)
+    {"depth": study_depth, "minmatch": study_minmatch, "corpora": study_corpora, "seek": study_seek,
+     "streamdiff": study_streamdiff}[args.study](args)
 
 
 if __name__ == "__main__":
