@@ -1807,21 +1807,6 @@ __device__ inline uint32_t jump_broken(DevStatus* st, uint32_t where) {
   return kJRes;
 }
 
-// Before the bulk rounds: the leftover map starts empty (the last round sets
-// its bits) and every window block records where its output bytes start.
-template <class O>
-__global__ __launch_bounds__(kCopyThreads) void k_jprep(JumpArgs a) {
-  const uint64_t words = uint64_t(a.n_items) * (a.S / 64);
-  for (uint64_t g = uint64_t(blockIdx.x) * kCopyThreads + threadIdx.x; g < words;
-       g += uint64_t(gridDim.x) * kCopyThreads)
-    a.lmap[g] = 0;
-  for (uint32_t x = blockIdx.x * kCopyThreads + threadIdx.x; x < a.n_items; x += gridDim.x * kCopyThreads) {
-    const WinBlock wb = a.wbl[x];
-    const JobDev& jd = a.jobs[wb.job];
-    a.ibase[x] = (uint8_t*)(O(jd).at(wb.b * jd.B));
-  }
-}
-
 // Long pending tokens: one workgroup per token, eight bytes per thread per
 // pass (first entries as in the marking of a round, bits by global atomics).
 template <class O>
@@ -2125,12 +2110,6 @@ __global__ void k_slots(uint32_t* slot, const WinBlock* wbl, uint32_t n_items) {
 }
 
 // Zero two word ranges (one launch for both).
-__global__ void k_clear2(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) q[i] = 0;
-}
-
-// Status reset before each window (the first also clears the error word).
 // The tokens round 0 left: the sum of its sublist counters (one wave).
 __global__ void k_pending0(const uint32_t* cnt, DevStatus* st) {
   uint32_t tot;
@@ -2138,18 +2117,56 @@ __global__ void k_pending0(const uint32_t* cnt, DevStatus* st) {
   if (threadIdx.x == 0) st->pend0 = tot;
 }
 
+// Status reset before each window (the first also clears the error word).
+__device__ inline void window_status_reset(DevStatus* st, int first) {
+  if (first) {
+    st->err = 0;
+    st->bad_block = ~0ull;
+  }
+  st->ticket = 0;
+  st->long_count = 0;
+  st->n_pending = 0;
+  st->jump_used = 0;
+  st->n_jwords = 0;
+  st->pend0 = 0;
+}
+
 __global__ void k_window_init(DevStatus* st, int first) {
-  if (threadIdx.x == 0) {
-    if (first) {
-      st->err = 0;
-      st->bad_block = ~0ull;
-    }
-    st->ticket = 0;
-    st->long_count = 0;
-    st->n_pending = 0;
-    st->jump_used = 0;
-    st->n_jwords = 0;
-    st->pend0 = 0;
+  if (threadIdx.x == 0) window_status_reset(st, first);
+}
+
+// Everything a window's match layer needs zeroed or precomputed, in one
+// launch before its entropy stage: the status words, the list counters and
+// pass flags, the persistent chase's leftover bitmap, and for pointer
+// jumping the leftover map (the last round sets its bits) and where every
+// window block's output bytes start.
+struct PrepArgs {
+  DevStatus* st;
+  int first;
+  uint32_t* counts;
+  uint32_t n_counts;
+  uint32_t* pbits;
+  uint32_t n_pbits;
+  uint64_t* lmap;  // null: no jump in this window
+  uint64_t n_lmap;
+  uint8_t** ibase;
+  const JobDev* jobs;
+  const WinBlock* wbl;
+  uint32_t n_items;
+};
+
+template <class O>
+__global__ __launch_bounds__(kCopyThreads) void k_window_prep(PrepArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) window_status_reset(a.st, a.first);
+  const uint64_t i0 = uint64_t(blockIdx.x) * kCopyThreads + threadIdx.x, step = uint64_t(gridDim.x) * kCopyThreads;
+  for (uint64_t i = i0; i < a.n_counts; i += step) a.counts[i] = 0;
+  for (uint64_t i = i0; i < a.n_pbits; i += step) a.pbits[i] = 0;
+  if (!a.lmap) return;
+  for (uint64_t i = i0; i < a.n_lmap; i += step) a.lmap[i] = 0;
+  for (uint64_t x = i0; x < a.n_items; x += step) {
+    const WinBlock wb = a.wbl[x];
+    const JobDev& jd = a.jobs[wb.job];
+    a.ibase[x] = (uint8_t*)(O(jd).at(wb.b * jd.B));
   }
 }
 
@@ -2744,8 +2761,21 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
     const Plan::Win& W = P->wins[wi];
     const bool first = wi == 0;
     const WinBlock* wbl = P->d_wbl + W.at;
-    hipLaunchKernelGGL(k_window_init, dim3(1), dim3(64), 0, s, st, int(first));
     uint32_t* counts = reinterpret_cast<uint32_t*>(w + L.counts);
+    const uint32_t ntok = W.tok;
+    const bool jump = P->opt.tail_mode == 0 && copy_mode != AX_COPY_SERIAL;
+    const uint32_t n_words = (ntok + 31) / 32;
+    const uint64_t mwords = uint64_t(W.items) * (P->slot_b / 64);  // leftover-map words
+    // eight listed words per wave step, four waves per workgroup
+    const uint32_t jgrid = uint32_t(std::min<uint64_t>((mwords + 31) / 32, kJMaxGrid));
+    {
+      const bool jmap = jump && ntok;
+      const PrepArgs pr{st, int(first), counts, uint32_t((L.jflags - L.counts) / 4 + kJPasses * kJShards * kJFlagStride),
+                        reinterpret_cast<uint32_t*>(w + L.pbits), ntok ? n_words : 0u,
+                        jmap ? reinterpret_cast<uint64_t*>(w + L.lmap) : nullptr, mwords,
+                        reinterpret_cast<uint8_t**>(w + L.ibase), P->d_jobs, wbl, W.items};
+      hipLaunchKernelGGL(k_window_prep<O>, dim3(std::max(1u, jgrid)), dim3(kCopyThreads), 0, s, pr);
+    }
     AnsArgs aa{P->d_jobs, wbl, W.items, P->slot_b, w + L.lit, w + L.cmd, w + L.off, w + L.len, P->off_cap,
                P->len_cap, reinterpret_cast<uint32_t*>(w + L.nsym), st};
     hipEvent_t* ev = timed ? P->ev.data() + 5 * wi : nullptr;
@@ -2760,17 +2790,11 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
     if (pa.mcov) hipLaunchKernelGGL((k_parse<O, true>), dim3(W.items), dim3(kParseThreads), 0, s, pa);
     else hipLaunchKernelGGL((k_parse<O, false>), dim3(W.items), dim3(kParseThreads), 0, s, pa);
     if (ev) (void)hipEventRecord(ev[2], s);
-    const uint32_t ntok = W.tok;
-    const bool jump = P->opt.tail_mode == 0 && copy_mode != AX_COPY_SERIAL;
     const int last_mark = jump ? kMarkJump : kMarkList;
     if (ntok) {
       uint32_t* lists[2] = {reinterpret_cast<uint32_t*>(w + L.list0), reinterpret_cast<uint32_t*>(w + L.list1)};
       auto cset = [&](int r) { return counts + (r % 3) * kSub * kCounterStride; };
-      const uint32_t n_words = (ntok + 31) / 32, pgrid = (n_words + kPackWords - 1) / kPackWords;
-      // the list counters and the leftover bitmap start at zero
-      hipLaunchKernelGGL(k_clear2, dim3(pgrid), dim3(256), 0, s, counts,
-                         uint32_t((L.jflags - L.counts) / 4 + kJPasses * kJShards * kJFlagStride),
-                         reinterpret_cast<uint32_t*>(w + L.pbits), n_words);
+      const uint32_t pgrid = (n_words + kPackWords - 1) / kPackWords;
       CopyArgs ca{P->d_jobs, wbl, W.items, reinterpret_cast<const uint64_t*>(w + L.tok),
                   reinterpret_cast<const uint32_t*>(w + L.tblk), ntok, reinterpret_cast<uint32_t*>(w + L.cov),
                   w + L.done, nullptr, lists[0], nullptr, cset(0), cset(1), uint32_t(L.sub_cap),
@@ -2786,10 +2810,6 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
                   reinterpret_cast<uint64_t*>(w + L.amap), reinterpret_cast<uint32_t*>(w + L.jflags),
                   reinterpret_cast<uint8_t**>(w + L.ibase), uint32_t(__builtin_ctz(P->slot_b)),
                   nullptr, nullptr, uint32_t(L.sub_cap), reinterpret_cast<uint32_t*>(w + L.wlist), st, 0};
-      const uint64_t mwords = uint64_t(W.items) * (P->slot_b / 64);  // leftover-map words
-      // eight listed words per wave step, four waves per workgroup
-      const uint32_t jgrid = uint32_t(std::min<uint64_t>((mwords + 31) / 32, kJMaxGrid));
-      if (jump) hipLaunchKernelGGL(k_jprep<O>, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
       const uint32_t grid = uint32_t(std::min<uint64_t>((ntok + kCopyThreads - 1) / kCopyThreads, kMaxRoundGrid));
       if (P->opt.round0_tile && ca.mcov)
         hipLaunchKernelGGL((k_round0<O, true>), dim3(W.items), dim3(kCopyThreads), 0, s, ca);

@@ -153,6 +153,17 @@ def test_depth_capped_archive():
     check("depth_cap2", x, arc)
 
 
+@pytest.mark.parametrize("kind,cap", [("text", 16), ("dna", 16)])
+def test_full_size_depth_capped(kind, cap):
+    """The full-size text and DNA workloads encoded under a depth cap (the
+    library's encoder iterates forced literals until no match is deeper than
+    the cap): the decode of the capped archive equals the input."""
+    x = synth.text(209715200, 3) if kind == "text" else synth.dna(15500 * B, 2)
+    arc, st = ax.encode(x, stats=True, threads=16, depth_cap=cap)
+    assert st.max_depth <= cap
+    check(f"full-{kind}-cap{cap}", x, arc, modes=(ax.COPY_PERIODIC,))
+
+
 # ---------------------------------------------------------- assembled cases --
 
 def _assemble_check(name, data, cmds, **kw):
