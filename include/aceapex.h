@@ -297,8 +297,10 @@ int aceapex_decoder_tokens(const aceapex_decoder* dec, uint64_t first, uint64_t 
 /* Source-closure size of each of n ranges on its own (blocks and matches),
  * on up to `threads` host threads (0: up to 16): what a request needs from a
  * range plan's limits, for admission by scratch memory before any launch.
- * The sizes of several ranges bound the size of their union.  Errors:
- * AX_E_ARG (index not built), AX_E_RANGE. */
+ * The sizes of several ranges bound the size of their union.  The closures
+ * found here are kept by the decoder (bounded) and reused when a later
+ * union closure (aceapex_decode_ranges, aceapex_closure_blocks) meets the
+ * same range.  Errors: AX_E_ARG (index not built), AX_E_RANGE. */
 int aceapex_closure_sizes(const aceapex_decoder* dec, uint32_t n, const uint64_t* offs, const uint64_t* lens,
                           uint64_t* blocks, uint64_t* tokens, uint32_t threads);
 

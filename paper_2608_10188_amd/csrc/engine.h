@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "aceapex.h"
@@ -81,6 +83,16 @@ int workspace_status(void* d_work, hipStream_t s, int32_t* dev_err, uint64_t* ba
 
 }  // namespace ax
 
+namespace ax {
+struct RangeKey {
+  uint64_t off, len;
+  bool operator==(const RangeKey& o) const { return off == o.off && len == o.len; }
+};
+struct RangeKeyHash {
+  size_t operator()(const RangeKey& k) const { return size_t(k.off * 0x9E3779B97F4A7C15ull ^ (k.len + (k.off >> 29))); }
+};
+}  // namespace ax
+
 // The decoder handle: a host copy of the archive's header and index, the
 // device archive, and the plan of a whole-archive decode.
 struct aceapex_decoder {
@@ -91,4 +103,9 @@ struct aceapex_decoder {
   ax::Plan* plan = nullptr;
   std::vector<uint64_t> idx_src, idx_dstlen;  // token index (aceapex_decoder_build_index)
   aceapex_range_plan* range = nullptr;        // aceapex_decode_range's plan (created on first use)
+  // closures of single ranges already found (ascending blocks), so that a
+  // batch's union does not walk again what admission walked; bounded
+  mutable std::mutex ccache_mu;
+  mutable std::unordered_map<ax::RangeKey, std::vector<uint64_t>, ax::RangeKeyHash> ccache;
+  mutable uint64_t ccache_blocks = 0;
 };

@@ -140,6 +140,22 @@ void closure_of(const aceapex_decoder* d, uint64_t off, uint64_t len, NeedSet& n
   }
 }
 
+// The closure cache: lookups and bounded inserts (cleared when it holds more
+// than 2^22 block entries).
+bool cached_closure(const aceapex_decoder* d, uint64_t off, uint64_t len, std::vector<uint64_t>& out) {
+  std::lock_guard<std::mutex> lock(d->ccache_mu);
+  auto it = d->ccache.find(ax::RangeKey{off, len});
+  if (it == d->ccache.end()) return false;
+  out.insert(out.end(), it->second.begin(), it->second.end());
+  return true;
+}
+void cache_closure(const aceapex_decoder* d, uint64_t off, uint64_t len, const uint64_t* b, size_t n) {
+  std::lock_guard<std::mutex> lock(d->ccache_mu);
+  if (d->ccache_blocks + n > (uint64_t(1) << 22)) d->ccache.clear(), d->ccache_blocks = 0;
+  auto& v = d->ccache[ax::RangeKey{off, len}];
+  if (v.empty()) v.assign(b, b + n), d->ccache_blocks += n;
+}
+
 // Closures of many ranges in parallel, merged into one ascending block list.
 int union_closure(const aceapex_decoder* d, uint32_t n, const uint64_t* offs, const uint64_t* lens,
                   std::vector<uint64_t>& blocks, uint32_t threads) {
@@ -154,7 +170,7 @@ int union_closure(const aceapex_decoder* d, uint32_t n, const uint64_t* offs, co
     for (;;) {
       const uint32_t i = next.fetch_add(1);
       if (i >= n) break;
-      if (!lens[i]) continue;
+      if (!lens[i] || cached_closure(d, offs[i], lens[i], part[w])) continue;
       NeedSet need(d->info.block_size);
       closure_of(d, offs[i], lens[i], need);
       need.blocks(part[w]);
@@ -404,11 +420,12 @@ int aceapex_closure_sizes(const aceapex_decoder* d, uint32_t n, const uint64_t* 
       const uint32_t i = next.fetch_add(1);
       if (i >= n) break;
       bl.clear();
-      if (lens[i]) {
+      if (lens[i] && !cached_closure(d, offs[i], lens[i], bl)) {
         try {
           NeedSet need(d->info.block_size);
           closure_of(d, offs[i], lens[i], need);
           need.blocks(bl);
+          cache_closure(d, offs[i], lens[i], bl.data(), bl.size());
         } catch (const std::bad_alloc&) {
           failed = 1;
           break;
