@@ -35,6 +35,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "aceapex.h"
@@ -149,6 +150,9 @@ __device__ inline void report(DevStatus* st, int code, uint64_t block) {
 }
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
+// Fourth word of a raw buffer descriptor on gfx9-family parts (32-bit data
+// format; untyped byte stores ignore it)
+constexpr int kBufferWord3 = 0x00020000;
 
 __device__ inline uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
@@ -326,42 +330,62 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
   }
   __syncthreads();
   // --- decode: lane j owns symbols j, j+K, ...
+  // The renormalisation words of a step are taken in lane order from a
+  // window: lane l's register P holds word base+l in its low half and word
+  // base+64+l in its high half, N holds word base+128+l (in flight while the
+  // window is used).  A step's words lie in [ptr, ptr+64) with ptr-base < 64,
+  // so one permute of P from lane (ptr-base+below) mod 64 and a byte select
+  // of the half give each lane its word.  Once ptr-base reaches 64 the window
+  // moves by 64: P takes its high half and N's word, and N is reloaded.  Loads
+  // are unconditional, the index clamped to the last word (inside the record;
+  // a valid stream never consumes a word past nw)
   const AX_GLOBAL uint16_t* words = gp(reinterpret_cast<const uint16_t*>(rec + words_at));
   uint32_t x = lane < K ? ld32(rec + states_at + 4 * lane) : ax::kRansLow;
   bad = x < ax::kRansLow;
-  auto fetch = [&](uint32_t i) -> uint32_t { return i < nw ? uint32_t(words[i]) : 0u; };
-  uint32_t base = 0;  // window: wa = words[base+lane], w1 = words[base+64+lane], w2 = words[base+128+lane]
-  uint32_t wa = fetch(lane), w1 = fetch(64 + lane), w2 = fetch(128 + lane);
+  const uint32_t wlast = nw ? nw - 1 : 0;
+  auto fetch = [&](uint32_t i) -> uint32_t { return uint32_t(words[i < wlast ? i : wlast]); };
+  uint32_t base = 0;
+  uint32_t P = fetch(lane) | (fetch(64 + lane) << 16), N = fetch(128 + lane);
   uint32_t ptr = 0;
   const uint32_t steps = (n + K - 1) / K;
-  // steps with all K lanes decoding: no per-lane bounds, the store address
-  // a wave-uniform base plus the lane.  Every lane runs the step (the word
-  // permute reads all 64 lanes' window); lanes >= K are left out of the
-  // ballot and the store
-  const uint32_t full = n / K;
-  const uint64_t kmask = K == 64 ? ~0ull : ((1ull << K) - 1ull);
-  const bool decoding = lane < K;
-  AX_GLOBAL uint8_t* ob = out;
-  for (uint32_t t = 0; t < full; ++t, ob += K) {
-    const uint32_t slot = x & (ax::kProbScale - 1);
-    const uint32_t s = symtab[slot];
-    const uint32_t fc = fctab[s];
-    const uint32_t xn = (fc & 0xFFFFu) * (x >> ax::kProbBits) + slot - (fc >> 16);
-    const uint64_t m = __builtin_amdgcn_ballot_w64(xn < ax::kRansLow) & kmask;
-    const uint32_t q = ptr - base + lanes_below(m);  // < 128; the permute takes the lane mod 64
-    const uint32_t va = __builtin_amdgcn_ds_bpermute(int(q << 2), int(wa));
-    const uint32_t vb = __builtin_amdgcn_ds_bpermute(int(q << 2), int(w1));
-    const uint32_t w = q < 64 ? va : vb;
-    x = xn < ax::kRansLow ? ((xn << 16) | w) : xn;
-    if (decoding) ob[lane] = uint8_t(s);
+  // one step for the lanes in `need` (a subset of the decoding lanes):
+  // returns the new state of a lane from its decoded xn
+  auto renorm = [&](uint64_t m, uint32_t xn, bool need) -> uint32_t {
+    const uint32_t q = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)) +
+                       (ptr - base);  // < 128; the permute takes the lane mod 64
+    const uint32_t v = __builtin_amdgcn_ds_bpermute(int(q << 2), int(P));
+    // (xn << 16) | the word: xn's two low bytes above v's low or high half
+    const uint32_t xr = __builtin_amdgcn_perm(xn, v, q < 64 ? 0x05040100u : 0x05040302u);
     ptr += __popcll(m);
     if (ptr - base >= 64) {
       base += 64;
-      wa = w1;
-      w1 = w2;
-      w2 = fetch(base + 128 + lane);
+      P = __builtin_amdgcn_perm(N, P, 0x05040302u);
+      N = fetch(base + 128 + lane);
     }
-  }
+    return need ? xr : xn;
+  };
+  // Steps with all K lanes decoding: no per-lane bounds; symbols leave
+  // through a buffer store addressed by the lane plus a wave-uniform offset.
+  // With K = 64 neither the ballot nor the store needs a lane mask
+  const uint32_t full = n / K;
+  const uint64_t kmask = K == 64 ? ~0ull : ((1ull << K) - 1ull);
+  const __amdgpu_buffer_rsrc_t orsrc = __builtin_amdgcn_make_buffer_rsrc(outs[stream], 0, int(n), kBufferWord3);
+  auto full_steps = [&](auto all_tag) {
+    constexpr bool kAll = decltype(all_tag)::value;
+    for (uint32_t t = 0; t < full; ++t) {
+      const uint32_t slot = x & (ax::kProbScale - 1);
+      const uint32_t s = symtab[slot];
+      const uint32_t fc = fctab[s];
+      const uint32_t xn = (fc & 0xFFFFu) * (x >> ax::kProbBits) + slot - (fc >> 16);
+      const bool need = xn < ax::kRansLow;
+      uint64_t m = __builtin_amdgcn_ballot_w64(need);
+      if (!kAll) m &= kmask;
+      if (kAll || lane < K) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(s), orsrc, int(lane), int(t * K), 0);
+      x = renorm(m, xn, need);
+    }
+  };
+  if (K == 64) full_steps(std::true_type{});
+  else full_steps(std::false_type{});
   uint32_t i = full * K + lane;
   for (uint32_t t = full; t < steps; ++t, i += K) {
     const bool act = lane < K && i < n;
@@ -370,21 +394,10 @@ __global__ __launch_bounds__(64) void k_ans(AnsArgs a) {
     const uint32_t fc = fctab[s];
     const uint32_t xn = (fc & 0xFFFFu) * (x >> ax::kProbBits) + slot - (fc >> 16);
     const bool need = act && xn < ax::kRansLow;
-    const uint64_t m = __ballot(need);
-    const uint32_t q = ptr - base + lanes_below(m);  // < 128
-    const uint32_t va = __builtin_amdgcn_ds_bpermute(int((q & 63) << 2), int(wa));
-    const uint32_t vb = __builtin_amdgcn_ds_bpermute(int((q & 63) << 2), int(w1));
-    const uint32_t w = q < 64 ? va : vb;
+    const uint32_t xr = renorm(__ballot(need), xn, need);
     if (act) {
-      x = need ? ((xn << 16) | w) : xn;
+      x = xr;
       out[i] = uint8_t(s);
-    }
-    ptr += __popcll(m);
-    if (ptr - base >= 64) {
-      base += 64;
-      wa = w1;
-      w1 = w2;
-      w2 = fetch(base + 128 + lane);
     }
   }
   bad |= lane < K && x != ax::kRansLow;
