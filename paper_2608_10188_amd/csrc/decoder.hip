@@ -1853,23 +1853,34 @@ __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
     uint64_t cb = ~0ull;  // the source block last looked up, kept over the lane's passes
     uint32_t cbase = 0;
     bool cin = false;
-    for (uint32_t k0 = lane * kJMarkBytes; k0 < len; k0 += kCopyThreads * kJMarkBytes) {
-      uint64_t j = dist > k0 ? k0 : uint64_t(k0 % uint32_t(dist));
-      uint32_t mw = ~0u, mbits = 0;
-      for (uint32_t k = k0; k < k0 + kJMarkBytes && k < len; ++k) {
+    // byte k of the token goes to lane k mod 256, so each wave store covers
+    // 64 consecutive entries; a wave's 64 positions meet at most three words
+    // of the leftover map, set by three lanes from the wave's ballot
+    const uint32_t d0 = item * a.S + uint32_t(dst - bs);  // window position of the token's first byte
+    const bool wrap = dist < len;                          // a periodic fill: sources repeat every dist bytes
+    const uint32_t per = wrap ? uint32_t(dist) : 0u;
+    const uint32_t jstep = wrap ? kCopyThreads % per : kCopyThreads;
+    uint32_t j = wrap ? lane % per : lane;  // source index of byte k
+    const uint32_t wl = lane & 63u, wofs = lane & ~63u;
+    for (uint32_t kb = 0; kb < len; kb += kCopyThreads) {
+      const uint32_t k = kb + lane;
+      const bool valid = k < len;
+      if (valid) {
         const uint64_t sp = src + j, sb = sp >> lb;
         if (sb != cb) cb = sb, cin = window_block(a.wbl, a.S, wb, sb, cbase);
-        const uint32_t v = cin ? cbase + uint32_t(sp & (jd.B - 1)) : kJRes | *O(jd).at(sp);
-        const uint32_t d = item * a.S + uint32_t(dst - bs) + k;
-        J[d] = v;
-        if ((d >> 5) != mw) {
-          if (mbits) atomicOr(&lm32[mw], mbits);
-          mw = d >> 5, mbits = 0;
-        }
-        mbits |= 1u << (d & 31);
-        if (++j == dist) j = 0;
+        J[d0 + k] = cin ? cbase + uint32_t(sp & (jd.B - 1)) : kJRes | *O(jd).at(sp);
       }
-      if (mbits) atomicOr(&lm32[mw], mbits);
+      const uint64_t m = __ballot(valid);
+      if (m && wl < 3) {
+        const uint32_t p0 = d0 + kb + wofs, off = p0 & 31u;  // the wave's first position
+        uint32_t bits;
+        if (wl == 0) bits = uint32_t(m << off);
+        else if (wl == 1) bits = off ? uint32_t(m >> (32 - off)) : uint32_t(m >> 32);
+        else bits = off ? uint32_t(m >> (64 - off)) : 0u;
+        if (bits) atomicOr(&lm32[(p0 >> 5) + wl], bits);
+      }
+      j += jstep;
+      if (wrap && j >= per) j -= per;
     }
   }
 }
