@@ -887,6 +887,7 @@ struct CopyArgs {
   uint32_t S;                 // position stride of a window block
   const uint64_t* mcov;       // match coverage of the window positions (the parse writes it when round 0
                               // is the only bulk round; null: round 0 finds every cover)
+  uint32_t one_job;           // 1: the plan has one job, so every token's output is jobs[0]'s
 };
 
 __device__ inline void token_at(const uint64_t* tok, uint64_t t, uint64_t& src, uint64_t& dst, uint32_t& len) {
@@ -1578,11 +1579,18 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
     O out(a.jobs[0]);
     if (act) {
       token_at(a.tok, t, src, dst, len);
-      out = token_out<O>(a, t);
+      if (!a.one_job) out = token_out<O>(a, t);
       cover_of(a, t, src, dst, len, lo, cnt);
     }
+    // the covering tokens' done flags, four loads in flight at a time
     bool ready = act;
-    for (uint32_t i = 0; i < cnt && ready; ++i) ready = a.done[lo + i] < a.round;
+    for (uint32_t i0 = 0; i0 < cnt && ready; i0 += 4) {
+      uint8_t f[4];
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) f[q] = i0 + q < cnt ? a.done[lo + i0 + q] : uint8_t(0);
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) ready = ready && f[q] < a.round;
+    }
     fill_ready<false>(out, ready, dst, src, len, a.serial, a.fill_round, fs);
     if (ready) a.done[t] = uint8_t(a.round);
     const bool left = act && !ready;
@@ -2826,7 +2834,8 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
                   reinterpret_cast<uint32_t*>(w + L.pbits), reinterpret_cast<const uint32_t*>(w + L.plist),
                   bulk <= 1 ? last_mark : 0, 1ull << 22, copy_mode == AX_COPY_SERIAL, P->opt.fill_round,
                   P->opt.fill_tail, uint32_t(P->opt.tail_chunks), reinterpret_cast<uint32_t*>(w + L.lit),
-                  reinterpret_cast<uint64_t*>(w + L.lmap), P->slot_b, pa.mcov ? reinterpret_cast<const uint64_t*>(w + L.mcov) : nullptr};
+                  reinterpret_cast<uint64_t*>(w + L.lmap), P->slot_b, pa.mcov ? reinterpret_cast<const uint64_t*>(w + L.mcov) : nullptr,
+                  P->jobs.size() == 1 ? 1u : 0u};
       // pointer jumping over window positions (the deep remainder); the
       // jump array is the stream slots, dead once the parse is through
       JumpArgs ja{P->d_jobs, wbl, W.items, ntok, P->slot_b, ca.tok, ca.tblk, ca.done,
