@@ -2253,6 +2253,9 @@ struct Plan {
   // which exits at once and reports it again); the gather finishes any
   // entry the passes leave, so the count never changes a byte
   std::vector<uint32_t> jpass;
+  // per window, the passes the device reported as needed (0: not known);
+  // once every window's count is known the spare pass is dropped
+  std::vector<uint32_t> jneed;
   // pinned: per window, the passes that found work and the tokens round 0
   // filled (two words)
   uint32_t* h_jused = nullptr;
@@ -2429,6 +2432,7 @@ static int build_tables(Plan* P, const std::vector<JobSpec>& specs) {
     P->mapped = !specs.empty() && specs[0].slot != nullptr;
     P->jpass.assign(P->wins.size(), 0);
     for (size_t i = 0; i < P->wins.size(); ++i) P->jpass[i] = jump_pass_bound(P->wins[i].tok);
+    P->jneed.assign(P->wins.size(), 0);
     P->jsettled = false;
     P->wbulk.assign(P->wins.size(), 0);
     P->bsettled = false;
@@ -2879,7 +2883,10 @@ static void enqueue_out(Plan* P, uint8_t* w, int copy_mode, hipStream_t s, bool 
         const uint32_t lgrid = uint32_t((mwords + kJListWords - 1) / kJListWords);
         hipLaunchKernelGGL(k_jlist, dim3(lgrid), dim3(kCopyThreads), 0, s, ja);
         hipLaunchKernelGGL(k_jinit, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
-        const uint32_t passes = P->opt.jump_passes ? std::min<uint32_t>(P->jpass[wi], P->opt.jump_passes) : P->jpass[wi];
+        // passes 0 .. used-1 leave no active entry (pass `used` found none);
+        // the spare pass that reports it again runs only while learning
+        uint32_t passes = P->jsettled && P->jneed[wi] ? std::min(P->jpass[wi], P->jneed[wi]) : P->jpass[wi];
+        if (P->opt.jump_passes) passes = std::min<uint32_t>(passes, P->opt.jump_passes);
         for (uint32_t p = 0; p < passes; ++p) {
           ja.pass = p;
           hipLaunchKernelGGL(k_jpass, dim3(jgrid), dim3(kCopyThreads), 0, s, ja);
@@ -2942,11 +2949,12 @@ static int run_plan(Plan* P, void* d_work, uint64_t work_len, int copy_mode, hip
         if (b != P->wbulk[i]) {
           P->wbulk[i] = b;
           P->jpass[i] = jump_pass_bound(P->wins[i].tok);
+          P->jneed[i] = 0;
           all = false;
           continue;
         }
       }
-      if (used) P->jpass[i] = std::min(P->jpass[i], used + 1);
+      if (used) P->jpass[i] = std::min(P->jpass[i], used + 1), P->jneed[i] = used;
       else all = false;
     }
     if (P->bulk_auto) P->bsettled = true;

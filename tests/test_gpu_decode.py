@@ -263,6 +263,57 @@ def test_deep_cross_block_chain():
     check("deep_chain", data, arc)
 
 
+@pytest.mark.parametrize("rounds", [0, 2, 4])
+def test_deep_chain_of_long_periodic_fills(rounds):
+    """Long self-overlapping matches deep in a cross-block chain.  Block b
+    holds a 300-byte match of block b-1's (chain depth b) and then a periodic
+    fill of 2000+ bytes over its own last p bytes, so with two or four bulk
+    rounds the deep ones reach the remainder as long pending tokens (marked
+    with their bytes 256 apart over a workgroup's lanes).  Periods below,
+    equal to and above 256 and unaligned destinations exercise the wrap of
+    the source index and the leftover-map words a wave's 64 bytes meet.
+    rounds 0: the learned count."""
+    rng = np.random.default_rng(5)
+    nb = 24
+    periods = [1, 3, 7, 64, 100, 255, 256, 257, 300, 511, 1000]
+    data = np.zeros(nb * B, np.uint8)
+    data[:B] = rng.integers(0, 256, B)
+    cmds = [(0, 0, B, 0, 0)]
+    prev = 0  # the previous block's chained match (block 0: literal bytes)
+    for b in range(1, nb):
+        s = b * B
+        h = 5 + 3 * b
+        data[s:s + h] = rng.integers(0, 256, h)
+        cmds.append((0, s, h, 0, 0))
+        a = s + h
+        data[a:a + 300] = data[prev:prev + 300]
+        cmds.append((1, a, 300, prev, 0))
+        p, f, ln = periods[b % len(periods)], a + 300, 2000 + 37 * b
+        data[f:f + ln] = np.resize(data[f - p:f], ln)
+        cmds.append((1, f, ln, f - p, 0))
+        t = f + ln
+        data[t:s + B] = rng.integers(0, 256, s + B - t)
+        cmds.append((0, t, s + B - t, 0, 0))
+        prev = a
+    arc = oracle.assemble(data, cmds)
+    ref = oracle.decode(arc)
+    assert np.array_equal(ref, data)
+    dec = ax.Decoder(arc, torch.from_numpy(arc).cuda())
+    if rounds:
+        dec.set_option(ax.OPT_BULK_ROUNDS, rounds)
+    out = torch.empty((data.size,), dtype=torch.uint8, device="cuda")
+    for k in range(3):
+        out.fill_(0xCC)
+        _say("long periodic chain: bulk rounds", rounds, "decode", k)
+        dec.decode_all(out=out)
+        err, bad = dec.status()
+        assert err == 0, (err, bad)
+        got = out.cpu().numpy()
+        if not np.array_equal(got, ref):
+            i = int(np.nonzero(got != ref)[0][0])
+            raise AssertionError(f"decode {k}: first mismatch at byte {i} (block {i // B})")
+
+
 # -------------------------------------------------------------- behaviour --
 
 @pytest.mark.parametrize("opts", [
