@@ -1449,10 +1449,20 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       const uint32_t dd = dist < n0 ? uint32_t(dist) : n0;  // the period (n0 when it never wraps)
       const uint32_t step = 64 % dd;
       uint32_t j = lane % dd;
-      for (uint32_t k = lane; k < n0; k += 64) {
-        tile[d0 + k] = *out.at(s0 + j);
-        j += step;
-        if (j >= dd) j -= dd;
+      for (uint32_t k0 = lane; k0 < n0; k0 += 512) {  // eight source loads in flight per lane
+        uint32_t jj[8];
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) {
+          jj[q] = j;
+          j += step;
+          if (j >= dd) j -= dd;
+        }
+        uint8_t v[8];
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) v[q] = k0 + 64 * q < n0 ? *out.at(s0 + jj[q]) : uint8_t(0);
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q)
+          if (k0 + 64 * q < n0) tile[d0 + k0 + 64 * q] = v[q];
       }
     }
   }
