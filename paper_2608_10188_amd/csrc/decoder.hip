@@ -662,6 +662,9 @@ __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
   if (t == 0)
     sh.bad = (n_lit > B || n_cmd > B || n_len > job_len_cap(J) || n_off > job_off_cap(J) ||
               tok_lo + tok_n > a.n_tok) ? 1 : 0;
+  // the first chunk's command bytes, loaded ahead of the staging barrier
+  // (inside the slot whatever the count: kParseThreads <= slot_b)
+  uint32_t cnext = cmd[t];
   // stage the offset and length streams in LDS (16-byte loads; slots are 16-aligned)
   if (n_off <= kOffStage)
     for (uint32_t k = 16 * t; k < n_off; k += 16 * kParseThreads)
@@ -683,7 +686,8 @@ __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
   for (uint32_t c0 = 0; c0 < n_cmd && !failed; c0 += kParseThreads) {
     const uint32_t i = c0 + t;
     const bool valid = i < n_cmd;
-    const uint32_t c = valid ? cmd[i] : 0u;
+    const uint32_t c = valid ? cnext : 0u;
+    cnext = i + kParseThreads < n_cmd ? cmd[i + kParseThreads] : 0u;  // the next chunk's, in flight meanwhile
     const uint32_t kind = c & 3;
     bool bad = valid && kind == 3;
     const uint32_t v = kind == 2 ? (c >> 4) : (c >> 2);
