@@ -665,13 +665,16 @@ __global__ __launch_bounds__(kParseThreads, 6) void k_parse(ParseArgs a) {
   // the first chunk's command bytes, loaded ahead of the staging barrier
   // (inside the slot whatever the count: kParseThreads <= slot_b)
   uint32_t cnext = cmd[t];
-  // stage the offset and length streams in LDS (16-byte loads; slots are 16-aligned)
-  if (n_off <= kOffStage)
-    for (uint32_t k = 16 * t; k < n_off; k += 16 * kParseThreads)
-      *reinterpret_cast<uint4*>(sh.offb + k) = *reinterpret_cast<const uint4*>(offs + k);
-  if (n_len <= kLenStage)
-    for (uint32_t k = 16 * t; k < n_len; k += 16 * kParseThreads)
-      *reinterpret_cast<uint4*>(sh.lenb + k) = *reinterpret_cast<const uint4*>(lens + k);
+  // stage the offset and length streams in LDS: one 16-byte piece per
+  // thread, loaded before the stream lengths are known (the slots are
+  // 16-aligned and their capacities multiples of 16, so the loads stay in
+  // this block's slots) and kept if the stream fits the stage
+  static_assert(kOffStage <= 16 * kParseThreads && kLenStage <= 16 * kParseThreads, "one piece per thread");
+  uint4 po = {0, 0, 0, 0}, pl = {0, 0, 0, 0};
+  if (16 * t < min(kOffStage, a.off_cap)) po = *reinterpret_cast<const uint4*>(offs + 16 * t);
+  if (16 * t < min(kLenStage, a.len_cap)) pl = *reinterpret_cast<const uint4*>(lens + 16 * t);
+  if (n_off <= kOffStage && 16 * t < n_off) *reinterpret_cast<uint4*>(sh.offb + 16 * t) = po;
+  if (n_len <= kLenStage && 16 * t < n_len) *reinterpret_cast<uint4*>(sh.lenb + 16 * t) = pl;
   __syncthreads();
   bool failed = sh.bad != 0;
   // the streams are read from LDS when staged, else from global memory (two
