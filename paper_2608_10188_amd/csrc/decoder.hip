@@ -1316,9 +1316,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   // only round (the coverage-map instantiation; the other one keeps its LDS
   // for one more resident workgroup)
   __shared__ uint32_t lft[kCovMap ? kMaxB / 32 : 1];
-  if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const uint32_t lane = lane_id(), item = xcd_item(blockIdx.x, gridDim.x);
-  if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
   const WinBlock wb = a.wbl[item];
   const JobDev& J = a.jobs[wb.job];
   const O out(J);
@@ -1329,6 +1327,9 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
   const uint32_t nchunk = (blen + 15) / 16;
   const uint32_t t1 = item + 1 < a.n_items ? a.wbl[item + 1].tok : a.n_tok;
   const uint32_t ntb = t1 - wb.tok;  // <= blen: tokens are at least a byte long
+  // the status is checked once the block's own loads are in flight
+  if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
   // the serial ablation reads in-block sources back from the tile: load all of it
   for (uint32_t k = threadIdx.x; k < kMaxB / 16 / 32; k += kCopyThreads) dirty[k] = a.serial ? ~0u : 0u;
   for (uint32_t k = threadIdx.x; k < (ntb + 31) / 32; k += kCopyThreads) {
@@ -1567,14 +1568,15 @@ __global__ __launch_bounds__(kCopyThreads) void k_round(CopyArgs a) {
   __shared__ FillStage stage[kCopyThreads / 64];
   __shared__ MarkStage mstage[kCopyThreads / 64];
   __shared__ uint32_t sub_end[kSub];  // inclusive prefix of the input sublist lengths
-  if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const uint32_t lane = lane_id();
   FillStage& fs = stage[threadIdx.x >> 6];
+  // the status is checked once the counters' loads are in flight
+  const uint32_t c_in = threadIdx.x < 64 ? a.cnt_in[threadIdx.x * kCounterStride] : 0u;
+  if (__hip_atomic_load(&a.st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   if (blockIdx.x == 0 && threadIdx.x < kSub) a.cnt_clear[threadIdx.x * kCounterStride] = 0;
   if (threadIdx.x < 64) {
     uint32_t tot;
-    const uint32_t c = a.cnt_in[threadIdx.x * kCounterStride];
-    sub_end[threadIdx.x] = wave_excl_sum(c, &tot) + c;
+    sub_end[threadIdx.x] = wave_excl_sum(c_in, &tot) + c_in;
   }
   __syncthreads();
   const uint32_t n_items = sub_end[kSub - 1];
