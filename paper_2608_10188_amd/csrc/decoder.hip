@@ -1847,8 +1847,9 @@ __device__ inline uint32_t jump_broken(DevStatus* st, uint32_t where) {
   return kJRes;
 }
 
-// Long pending tokens: one workgroup per token, eight bytes per thread per
-// pass (first entries as in the marking of a round, bits by global atomics).
+// Long pending tokens: one workgroup per token, byte k of the token on lane
+// k mod 256 (first entries as in the marking of a round, bits by global
+// atomics).
 template <class O>
 __global__ __launch_bounds__(kCopyThreads) void k_jmarklong(JumpArgs a) {
   __shared__ uint32_t sub_end[kSub];  // inclusive prefix of the sublist lengths
