@@ -218,9 +218,10 @@ enum { AX_OPT_ROUND0_TILE = 6 };
  *     matches (4096 by default), jumping above. */
 enum { AX_OPT_TAIL_MODE = 7 };
 /*   AX_OPT_JUMP_PASSES  0 = automatic: the first decode runs enough passes
- *     for any chain of the window (log3 of its token count) and later ones the
- *     count the device reported as needed, plus one; k in [1, 32] = at most k
- *     passes.  The final gather follows whatever entries the passes left, so
+ *     for any chain of the window (log3 of its token count), the next ones the
+ *     count the device reported as needed plus one (which reports it again),
+ *     and once every window's count is known exactly that count; k in
+ *     [1, 32] = at most k passes.  The final gather follows whatever entries the passes left, so
  *     the count changes timing only, never a byte. */
 enum { AX_OPT_JUMP_PASSES = 8 };
 /*   AX_OPT_RANGE_JUMP_TOKENS  range decodes of this decoder finish closures of
