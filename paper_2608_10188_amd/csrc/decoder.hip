@@ -1381,17 +1381,23 @@ __global__ __launch_bounds__(kCopyThreads) void k_round0(CopyArgs a) {
       if (kCovMap && left && a.mark == kMarkJump) atomicOr(&lft[(t - wb.tok) >> 5], 1u << ((t - wb.tok) & 31));
       continue;
     }
-    // a wave's tokens fall in at most two 64-token groups, hence two sublists
+    // a wave's tokens fall in at most two 64-token groups, hence two
+    // sublists: the first lane of each group reserves its group's places, both
+    // in one atomic instruction
     const uint32_t g0 = (base + (threadIdx.x & ~63u)) >> 6;
-#pragma unroll
-    for (uint32_t h = 0; h < 2; ++h) {
-      const uint64_t m = __ballot(left && (t >> 6) == g0 + h);
-      if (!m) continue;
-      const uint32_t sub = (g0 + h) % kSub, first = __builtin_ctzll(m);
+    const bool in0 = left && (t >> 6) == g0, in1 = left && (t >> 6) == g0 + 1;
+    const uint64_t m0 = __ballot(in0), m1 = __ballot(in1);
+    if (m0 | m1) {
+      const uint32_t f0 = m0 ? uint32_t(__builtin_ctzll(m0)) : 64u, f1 = m1 ? uint32_t(__builtin_ctzll(m1)) : 64u;
+      const uint32_t sub0 = g0 % kSub, sub1 = (g0 + 1) % kSub;
       uint32_t at = 0;
-      if (lane == first) at = atomicAdd(a.cnt_out + sub * kCounterStride, uint32_t(__popcll(m)));
-      at = __shfl(at, first, 64);
-      if (left && (t >> 6) == g0 + h) a.list_out[uint64_t(sub) * a.sub_cap + at + lanes_below(m)] = t;
+      if (lane == f0 || lane == f1) {  // a lane is in at most one group
+        const bool h = lane == f1;
+        at = atomicAdd(a.cnt_out + (h ? sub1 : sub0) * kCounterStride, uint32_t(__popcll(h ? m1 : m0)));
+      }
+      const uint32_t at0 = __shfl(at, int(f0 & 63u), 64), at1 = __shfl(at, int(f1 & 63u), 64);
+      if (in0) a.list_out[uint64_t(sub0) * a.sub_cap + at0 + lanes_below(m0)] = t;
+      if (in1) a.list_out[uint64_t(sub1) * a.sub_cap + at1 + lanes_below(m1)] = t;
     }
   }
   __syncthreads();
