@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 # each scaled by the same counter on a plain 256 MiB device copy in the same
 # run).  They hold only for the decoder source they were taken on (first 16
 # hex digits of its SHA-256); otherwise the line reports traffic null.
-TRAFFIC_SOURCE = "a69bc00321e7baec"
+TRAFFIC_SOURCE = "fb8af562ee6cd7c8"
 TRAFFIC_MB = 1952.3  # read + write MB per decode
 
 WORKLOADS = {

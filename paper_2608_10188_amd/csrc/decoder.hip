@@ -2127,6 +2127,7 @@ __global__ __launch_bounds__(kCopyThreads) void k_jgather(JumpArgs a) {
   const uint32_t lane = lane_id(), limit = a.n_items * a.S, omask = (1u << a.s_log2) - 1u;
   const AX_GLOBAL uint32_t* const J = gp(a.J);
   const uint32_t sub = lane >> 4, q4 = 4 * (lane & 15u);
+  static_assert(kJStepWords == 8, "the gather takes a group's words as two halves of four");
   walk_words(a, a.lmap, [&](const WordGroup& w) __attribute__((always_inline)) {
 #pragma unroll
     for (uint32_t h = 0; h < 2; ++h) {
