@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # run).  They hold only for the decoder source they were taken on (first 16
 # hex digits of its SHA-256); otherwise the line reports traffic null.
 TRAFFIC_SOURCE = "fb8af562ee6cd7c8"
-TRAFFIC_MB = 1952.3  # read + write MB per decode
+TRAFFIC_MB = 1952.4  # read + write MB per decode
 
 WORKLOADS = {
     # name: (generator, bytes, seed, description)
